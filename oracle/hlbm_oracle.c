@@ -1,0 +1,539 @@
+/*
+ * hlbm_oracle.c -- plain, slow FP64 CPU reference of one HLBM time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU baseline leg of
+ * the benchmark do.  It shares no source, table or helper with the HIP
+ * library: its velocity ordering, storage order (f[cell][i], push streaming,
+ * separate collide and stream passes) and every formula are written here from
+ * the paper (Marquardt, Hafen, Krause, arXiv 2312.14172, Sec. 3).
+ *
+ * Conventions (lattice units, Sec. 3.1):
+ *   cell (x,y,z) has centre (x+1/2, y+1/2, z+1/2) and index x + nx*(y + ny*z);
+ *   bc[k] = 0 periodic, 1 half-way bounce-back walls at 0 and n_k;
+ *   f is the post-streaming state at integer time t.
+ *
+ * Readings of points the paper leaves open are marked "reading:".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 19
+
+/* ---------------------------------------------------------------------------
+ * D3Q19 velocity set and weights (Sec. 3.1, velocity-set and weight equations).
+ * This file's own order: rest; +x,+y,+z,-x,-y,-z; then the twelve diagonals.
+ * ------------------------------------------------------------------------- */
+static const int C[Q][3] = {
+    {0, 0, 0},
+    {1, 0, 0},  {0, 1, 0},  {0, 0, 1},  {-1, 0, 0},  {0, -1, 0}, {0, 0, -1},
+    {1, 1, 0},  {1, -1, 0}, {1, 0, 1},  {1, 0, -1},  {0, 1, 1},  {0, 1, -1},
+    {-1, -1, 0}, {-1, 1, 0}, {-1, 0, -1}, {-1, 0, 1}, {0, -1, -1}, {0, -1, 1}};
+
+static double W[Q];
+static int OPP[Q];
+static int tables_ready = 0;
+
+static void init_tables(void) {
+    if (tables_ready) return;
+    for (int i = 0; i < Q; ++i) {
+        int c2 = C[i][0] * C[i][0] + C[i][1] * C[i][1] + C[i][2] * C[i][2];
+        /* weights: 1/3 rest, 1/18 axis, 1/36 diagonal */
+        W[i] = (c2 == 0) ? 1.0 / 3.0 : (c2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+        OPP[i] = -1;
+        for (int j = 0; j < Q; ++j)
+            if (C[j][0] == -C[i][0] && C[j][1] == -C[i][1] && C[j][2] == -C[i][2]) OPP[i] = j;
+    }
+    tables_ready = 1;
+}
+
+void orc_tables(int *c, double *w, int *opp) {
+    init_tables();
+    for (int i = 0; i < Q; ++i) {
+        for (int k = 0; k < 3; ++k) c[3 * i + k] = C[i][k];
+        w[i] = W[i];
+        opp[i] = OPP[i];
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Configuration and particle records (this file's own declarations).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int n[3];
+    int bc[3];
+    double tau;      /* relaxation time, tau = 3 nu + 1/2 (relaxation eq.) */
+    double eps;      /* smooth-boundary width of the indicator, 1/2 in the paper */
+    double rho_f;    /* fluid density used in the buoyancy term */
+    double g[3];     /* gravity vector */
+    double af[3];    /* fluid body acceleration (Poiseuille / sphere-array drag) */
+} ocfg;
+
+enum { SH_SPHERE = 0, SH_ROUNDED_CUBE = 1, SH_SPHEROID = 2 };
+
+typedef struct {
+    double X[3];   /* centre of mass */
+    double q[4];   /* unit quaternion (w,x,y,z), body -> world */
+    double U[3];   /* translational velocity */
+    double W[3];   /* angular velocity, world frame */
+    double m;      /* mass; <= 0 holds the particle fixed */
+    double V;      /* volume (buoyancy) */
+    double I[3];   /* principal moments of inertia, body frame */
+    double prm[3]; /* shape parameters */
+    int32_t shape;
+    int32_t flags;
+} opart;
+
+/* ---------------------------------------------------------------------------
+ * Equilibrium (Sec. 3.1, Maxwell-Boltzmann equation), c_s^2 = 1/3.
+ * ------------------------------------------------------------------------- */
+void orc_feq(double rho, const double *u, double *feq) {
+    init_tables();
+    const double cs2 = 1.0 / 3.0;
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < Q; ++i) {
+        double cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
+        feq[i] = W[i] * rho * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Signed distance functions, negative inside (Sec. 3.2, indicator paragraph).
+ * p is in the particle's body frame.
+ * reading: the paper's experiments use spheres only; the rounded cube and the
+ * spheroid use the exact Euclidean distance.
+ * ------------------------------------------------------------------------- */
+
+/* Distance from (y0,y1), y0,y1 >= 0, to the ellipse (u/e0)^2 + (v/e1)^2 = 1
+ * with e0 >= e1.  Unsigned.  The nearest point satisfies x_k = e_k^2 y_k /
+ * (t + e_k^2) for the root t of G(t) = sum_k (e_k y_k/(t+e_k^2))^2 - 1, which
+ * is bracketed by [e1 y1 - e1^2, |(e0 y0, e1 y1)| - e1^2] and found by plain
+ * bisection. */
+static double ellipse_dist_sorted(double e0, double e1, double y0, double y1) {
+    if (y1 > 0.0) {
+        if (y0 > 0.0) {
+            double lo = e1 * y1 - e1 * e1;
+            double hi = sqrt(e0 * e0 * y0 * y0 + e1 * e1 * y1 * y1) - e1 * e1;
+            for (int it = 0; it < 400; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                double a0 = e0 * y0 / (mid + e0 * e0);
+                double a1 = e1 * y1 / (mid + e1 * e1);
+                double G = a0 * a0 + a1 * a1 - 1.0;
+                if (G > 0.0) lo = mid; else hi = mid;
+            }
+            double t = 0.5 * (lo + hi);
+            double x0 = e0 * e0 * y0 / (t + e0 * e0);
+            double x1 = e1 * e1 * y1 / (t + e1 * e1);
+            return sqrt((x0 - y0) * (x0 - y0) + (x1 - y1) * (x1 - y1));
+        }
+        return fabs(y1 - e1); /* on the minor axis */
+    }
+    /* on the major axis */
+    double num = e0 * e0 - e1 * e1;
+    if (e0 * y0 < num) {
+        double x0 = e0 * e0 * y0 / num;
+        double r = x0 / e0;
+        double x1 = e1 * sqrt(fmax(0.0, 1.0 - r * r));
+        return sqrt((x0 - y0) * (x0 - y0) + x1 * x1);
+    }
+    return fabs(y0 - e0);
+}
+
+static double sdf_spheroid(double a, double b, const double *p) {
+    /* symmetry axis = body x, semi-axis a; the other two semi-axes are b */
+    double y0 = fabs(p[0]);
+    double y1 = sqrt(p[1] * p[1] + p[2] * p[2]);
+    double inside = (y0 / a) * (y0 / a) + (y1 / b) * (y1 / b) - 1.0;
+    double d = (a >= b) ? ellipse_dist_sorted(a, b, y0, y1) : ellipse_dist_sorted(b, a, y1, y0);
+    return inside <= 0.0 ? -d : d;
+}
+
+static double sdf_rounded_cube(double h, double rc, const double *p) {
+    /* Minkowski sum of a cube with half-extent h - rc and a ball of radius rc */
+    double core = h - rc;
+    double qx = fabs(p[0]) - core, qy = fabs(p[1]) - core, qz = fabs(p[2]) - core;
+    double ox = fmax(qx, 0.0), oy = fmax(qy, 0.0), oz = fmax(qz, 0.0);
+    double outside = sqrt(ox * ox + oy * oy + oz * oz);
+    double inside = fmin(fmax(qx, fmax(qy, qz)), 0.0);
+    return outside + inside - rc;
+}
+
+double orc_sdf(int shape, const double *prm, const double *p) {
+    switch (shape) {
+    case SH_SPHERE: return sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - prm[0];
+    case SH_ROUNDED_CUBE: return sdf_rounded_cube(prm[0], prm[1], p);
+    case SH_SPHEROID: return sdf_spheroid(prm[0], prm[1], p);
+    default: return 1e300;
+    }
+}
+
+/* Largest distance of the surface from the centre of mass. */
+double orc_circumradius(int shape, const double *prm) {
+    switch (shape) {
+    case SH_SPHERE: return prm[0];
+    case SH_ROUNDED_CUBE: return sqrt(3.0) * (prm[0] - prm[1]) + prm[1];
+    case SH_SPHEROID: return fmax(prm[0], prm[1]);
+    default: return 0.0;
+    }
+}
+
+/* Trigonometric indicator B(d_s) (Sec. 3.2, level-set equation).
+ * reading: the printed cosine argument has an unbalanced parenthesis; it is
+ * read as cos^2( (pi/2) (d/eps + 1/2) ), which is continuous with the outer
+ * pieces (1 at d = -eps/2, 0 at d = +eps/2). */
+double orc_indicator(double d, double eps) {
+    if (d <= -0.5 * eps) return 1.0;
+    if (d >= 0.5 * eps) return 0.0;
+    double c = cos(0.5 * M_PI * (d / eps + 0.5));
+    return c * c;
+}
+
+/* ---------------------------------------------------------------------------
+ * Geometry helpers
+ * ------------------------------------------------------------------------- */
+static void quat_to_rot(const double *q, double R[3][3]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0][0] = 1 - 2 * (y * y + z * z); R[0][1] = 2 * (x * y - w * z);     R[0][2] = 2 * (x * z + w * y);
+    R[1][0] = 2 * (x * y + w * z);     R[1][1] = 1 - 2 * (x * x + z * z); R[1][2] = 2 * (y * z - w * x);
+    R[2][0] = 2 * (x * z - w * y);     R[2][1] = 2 * (y * z + w * x);     R[2][2] = 1 - 2 * (x * x + y * y);
+}
+
+/* Separation of cell centre from the particle centre, minimum image on
+ * periodic axes (reading: torque lever arm and u_p(x) use it). */
+static void cell_offset(const ocfg *cfg, const opart *P, int ix, int iy, int iz, double *d) {
+    int idx[3] = {ix, iy, iz};
+    for (int k = 0; k < 3; ++k) {
+        double v = (idx[k] + 0.5) - P->X[k];
+        if (cfg->bc[k] == 0) v -= cfg->n[k] * nearbyint(v / cfg->n[k]);
+        d[k] = v;
+    }
+}
+
+static double particle_sdf_at(const opart *P, const double *d) {
+    double R[3][3], pb[3];
+    quat_to_rot(P->q, R);
+    for (int k = 0; k < 3; ++k) pb[k] = R[0][k] * d[0] + R[1][k] * d[1] + R[2][k] * d[2];
+    return orc_sdf(P->shape, P->prm, pb);
+}
+
+/* rigid-body velocity at offset d (Sec. 3.2, below the velocity-difference eq.) */
+static void rigid_velocity(const opart *P, const double *d, double *u) {
+    u[0] = P->U[0] + P->W[1] * d[2] - P->W[2] * d[1];
+    u[1] = P->U[1] + P->W[2] * d[0] - P->W[0] * d[2];
+    u[2] = P->U[2] + P->W[0] * d[1] - P->W[1] * d[0];
+}
+
+static long cell_index(const ocfg *cfg, int x, int y, int z) {
+    return (long)x + (long)cfg->n[0] * ((long)y + (long)cfg->n[1] * z);
+}
+
+/* Map an integer coordinate onto the lattice; returns 0 if it lies past a wall. */
+static int wrap_coord(const ocfg *cfg, int k, int v, int *out) {
+    int n = cfg->n[k];
+    if (v >= 0 && v < n) { *out = v; return 1; }
+    if (cfg->bc[k] != 0) return 0;
+    *out = ((v % n) + n) % n;
+    return 1;
+}
+
+/* Cells whose centre lies within `reach` of the particle centre along each
+ * axis, as an integer range [lo, hi]; wrapped later. */
+static void cell_range(const opart *P, int k, double reach, int *lo, int *hi) {
+    *lo = (int)ceil(P->X[k] - reach - 0.5);
+    *hi = (int)floor(P->X[k] + reach - 0.5);
+}
+
+/* ---------------------------------------------------------------------------
+ * Lattice-wide passes
+ * ------------------------------------------------------------------------- */
+long orc_ncells(const ocfg *cfg) { return (long)cfg->n[0] * cfg->n[1] * cfg->n[2]; }
+
+/* f = f^eq(rho, u) at every cell; rho, u may be NULL for rest (rho=1, u=0). */
+void orc_equilibrium_field(const ocfg *cfg, const double *rho, const double *u, double *f) {
+    init_tables();
+    long N = orc_ncells(cfg);
+    for (long x = 0; x < N; ++x) {
+        double uu[3] = {0, 0, 0}, r = 1.0;
+        if (rho) r = rho[x];
+        if (u) { uu[0] = u[x]; uu[1] = u[N + x]; uu[2] = u[2 * N + x]; }
+        orc_feq(r, uu, f + Q * x);
+    }
+}
+
+/* Bare moments (Sec. 3.1): rho = sum f_i, rho u = sum c_i f_i.  u is three planes. */
+void orc_moments(const ocfg *cfg, const double *f, double *rho, double *u) {
+    long N = orc_ncells(cfg);
+#pragma omp parallel for schedule(static) if (N >= 200000)
+    for (long x = 0; x < N; ++x) {
+        double r = 0, j[3] = {0, 0, 0};
+        for (int i = 0; i < Q; ++i) {
+            r += f[Q * x + i];
+            for (int k = 0; k < 3; ++k) j[k] += C[i][k] * f[Q * x + i];
+        }
+        rho[x] = r;
+        for (int k = 0; k < 3; ++k) u[k * N + x] = j[k] / r;
+    }
+}
+
+/* Collision with EDM source at one cell (collide, BGK and EDM equations):
+ *   rho, u from f;  du = B (u_s - u) + (1 - B) a_f;
+ *   f*_i = f_i - (f_i - feq_i(rho,u))/tau + feq_i(rho,u+du) - feq_i(rho,u).
+ * reading: the fluid velocity entering du and feq is the bare moment of the
+ * pre-collision populations; a_f is a body acceleration applied through the
+ * same exact-difference source outside the solid. */
+void orc_collide_cell(const ocfg *cfg, const double *f, double B, const double *us, double *fs) {
+    init_tables();
+    double rho = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+        rho += f[i];
+        for (int k = 0; k < 3; ++k) j[k] += C[i][k] * f[i];
+    }
+    double u[3], du[3], ud[3];
+    for (int k = 0; k < 3; ++k) u[k] = j[k] / rho;
+    for (int k = 0; k < 3; ++k) {
+        du[k] = B * (us[k] - u[k]) + (1.0 - B) * cfg->af[k];
+        ud[k] = u[k] + du[k];
+    }
+    double feq[Q], feqd[Q];
+    orc_feq(rho, u, feq);
+    orc_feq(rho, ud, feqd);
+    for (int i = 0; i < Q; ++i) {
+        double omega = -(f[i] - feq[i]) / cfg->tau;
+        double S = feqd[i] - feq[i];
+        fs[i] = f[i] + omega + S;
+    }
+}
+
+void orc_collide(const ocfg *cfg, const double *f, const double *B, const double *us, double *fs) {
+    long N = orc_ncells(cfg);
+#pragma omp parallel for schedule(static) if (N >= 200000)
+    for (long x = 0; x < N; ++x) {
+        double uu[3] = {us[x], us[N + x], us[2 * N + x]};
+        orc_collide_cell(cfg, f + Q * x, B[x], uu, fs + Q * x);
+    }
+}
+
+/* Streaming f_i(x + c_i, t+1) = f*_i(x, t) (stream equation), push form.
+ * reading: a population whose target lies past a wall returns to its own cell
+ * in the opposite direction (half-way bounce-back for resting walls). */
+void orc_stream(const ocfg *cfg, const double *fs, double *fn) {
+    init_tables();
+    int nx = cfg->n[0], ny = cfg->n[1], nz = cfg->n[2];
+    long N = orc_ncells(cfg);
+#pragma omp parallel for schedule(static) if (N >= 200000)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long s = cell_index(cfg, x, y, z);
+                for (int i = 0; i < Q; ++i) {
+                    int t[3], ok = 1;
+                    int v[3] = {x + C[i][0], y + C[i][1], z + C[i][2]};
+                    for (int k = 0; k < 3; ++k) ok &= wrap_coord(cfg, k, v[k], &t[k]);
+                    if (ok) fn[Q * cell_index(cfg, t[0], t[1], t[2]) + i] = fs[Q * s + i];
+                    else fn[Q * s + OPP[i]] = fs[Q * s + i];
+                }
+            }
+}
+
+/* ---------------------------------------------------------------------------
+ * Fluid -> particle: momentum exchange (Sec. 3.2, MEA, force and torque eqs.)
+ *   F_h(x) = sum_i (c_i - u_p(x)) f_i(x + c_i, t) + (c_i + u_p(x)) f_ibar(x, t)
+ * summed over the cells whose centre is inside the particle (d_s <= 0).
+ * reading: as printed, F_h is the momentum handed to the fluid; the force on
+ * the particle is its negative.  The sum over i covers both terms; i = 0
+ * contributes nothing.  A direction whose neighbour lies past a wall is
+ * skipped.  The lever arm is the minimum-image offset.
+ * ------------------------------------------------------------------------- */
+void orc_mea(const ocfg *cfg, int np, const opart *P, const double *f, double *F, double *T) {
+    init_tables();
+    for (int p = 0; p < np; ++p) {
+        double Fp[3] = {0, 0, 0}, Tp[3] = {0, 0, 0};
+        double reach = orc_circumradius(P[p].shape, P[p].prm) + 1.0;
+        int lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) cell_range(&P[p], k, reach, &lo[k], &hi[k]);
+        for (int a = lo[2]; a <= hi[2]; ++a)
+            for (int b = lo[1]; b <= hi[1]; ++b)
+                for (int c = lo[0]; c <= hi[0]; ++c) {
+                    int x[3];
+                    if (!wrap_coord(cfg, 0, c, &x[0]) || !wrap_coord(cfg, 1, b, &x[1]) ||
+                        !wrap_coord(cfg, 2, a, &x[2]))
+                        continue;
+                    double d[3];
+                    cell_offset(cfg, &P[p], x[0], x[1], x[2], d);
+                    if (particle_sdf_at(&P[p], d) > 0.0) continue; /* not in x_b */
+                    double up[3];
+                    rigid_velocity(&P[p], d, up);
+                    long xs = cell_index(cfg, x[0], x[1], x[2]);
+                    double Fh[3] = {0, 0, 0};
+                    for (int i = 1; i < Q; ++i) {
+                        int y[3], ok = 1;
+                        for (int k = 0; k < 3; ++k) ok &= wrap_coord(cfg, k, x[k] + C[i][k], &y[k]);
+                        if (!ok) continue;
+                        long ys = cell_index(cfg, y[0], y[1], y[2]);
+                        double fin = f[Q * ys + i];       /* f_i(x + c_i, t) */
+                        double fout = f[Q * xs + OPP[i]]; /* f_ibar(x, t) */
+                        for (int k = 0; k < 3; ++k)
+                            Fh[k] += (C[i][k] - up[k]) * fin + (C[i][k] + up[k]) * fout;
+                    }
+                    double tq[3] = {d[1] * Fh[2] - d[2] * Fh[1], d[2] * Fh[0] - d[0] * Fh[2],
+                                    d[0] * Fh[1] - d[1] * Fh[0]};
+                    for (int k = 0; k < 3; ++k) { Fp[k] -= Fh[k]; Tp[k] -= tq[k]; }
+                }
+        for (int k = 0; k < 3; ++k) { F[3 * p + k] = Fp[k]; T[3 * p + k] = Tp[k]; }
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * External force and equations of motion (Sec. 2.2, Newton and Euler eqs.;
+ * gravity and buoyancy of Sec. 5.1), dt = 1, FP64.
+ * reading: semi-implicit Euler; F_total = F_p + (m - rho_f V) g;
+ * the rotation is advanced in the body frame,
+ *   w_b <- w_b + I^-1 (T_b - w_b x (I w_b)),
+ * and the orientation by the exponential map q <- q (x) exp(w_b / 2).
+ * Fixed particles (m <= 0) are left untouched.
+ * ------------------------------------------------------------------------- */
+static void quat_mul(const double *a, const double *b, double *o) {
+    o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+void orc_apply_eom(const ocfg *cfg, int np, opart *P, const double *F, const double *T) {
+    for (int p = 0; p < np; ++p) {
+        opart *s = &P[p];
+        if (s->m <= 0.0) continue;
+        double Ft[3];
+        for (int k = 0; k < 3; ++k) Ft[k] = F[3 * p + k] + (s->m - cfg->rho_f * s->V) * cfg->g[k];
+        for (int k = 0; k < 3; ++k) {
+            s->U[k] += Ft[k] / s->m;
+            s->X[k] += s->U[k];
+            if (cfg->bc[k] == 0) s->X[k] -= cfg->n[k] * floor(s->X[k] / cfg->n[k]);
+        }
+        double R[3][3];
+        quat_to_rot(s->q, R);
+        double wb[3], tb[3];
+        for (int k = 0; k < 3; ++k) {
+            wb[k] = R[0][k] * s->W[0] + R[1][k] * s->W[1] + R[2][k] * s->W[2];
+            tb[k] = R[0][k] * T[3 * p + 0] + R[1][k] * T[3 * p + 1] + R[2][k] * T[3 * p + 2];
+        }
+        double Iw[3] = {s->I[0] * wb[0], s->I[1] * wb[1], s->I[2] * wb[2]};
+        double gyro[3] = {wb[1] * Iw[2] - wb[2] * Iw[1], wb[2] * Iw[0] - wb[0] * Iw[2],
+                          wb[0] * Iw[1] - wb[1] * Iw[0]};
+        for (int k = 0; k < 3; ++k) wb[k] += (tb[k] - gyro[k]) / s->I[k];
+        double ang = sqrt(wb[0] * wb[0] + wb[1] * wb[1] + wb[2] * wb[2]);
+        double dq[4] = {1, 0, 0, 0};
+        if (ang > 0.0) {
+            double sh = sin(0.5 * ang) / ang;
+            dq[0] = cos(0.5 * ang);
+            dq[1] = sh * wb[0]; dq[2] = sh * wb[1]; dq[3] = sh * wb[2];
+        }
+        double qn[4];
+        quat_mul(s->q, dq, qn);
+        double nq = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+        for (int k = 0; k < 4; ++k) s->q[k] = qn[k] / nq;
+        quat_to_rot(s->q, R);
+        for (int k = 0; k < 3; ++k) s->W[k] = R[k][0] * wb[0] + R[k][1] * wb[1] + R[k][2] * wb[2];
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Particle -> lattice: indicator and solid velocity fields (Sec. 3.2).
+ * reading (overlap of smoothed regions, not covered by the paper):
+ *   S0 = sum_p B_p, S1 = sum_p B_p u_p(x); B = min(1, S0), u_s = S1 / S0.
+ * Cells farther than R_circ + eps/2 from the centre have d_s >= eps/2 and
+ * B = 0, so only that box is visited.
+ * ------------------------------------------------------------------------- */
+void orc_coupling(const ocfg *cfg, int np, const opart *P, double *B, double *us) {
+    long N = orc_ncells(cfg);
+    double *S0 = (double *)calloc((size_t)N, sizeof(double));
+    double *S1 = (double *)calloc((size_t)N * 3, sizeof(double));
+    for (int p = 0; p < np; ++p) {
+        double reach = orc_circumradius(P[p].shape, P[p].prm) + 0.5 * cfg->eps;
+        int lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) cell_range(&P[p], k, reach, &lo[k], &hi[k]);
+        for (int a = lo[2]; a <= hi[2]; ++a)
+            for (int b = lo[1]; b <= hi[1]; ++b)
+                for (int c = lo[0]; c <= hi[0]; ++c) {
+                    int x[3];
+                    if (!wrap_coord(cfg, 0, c, &x[0]) || !wrap_coord(cfg, 1, b, &x[1]) ||
+                        !wrap_coord(cfg, 2, a, &x[2]))
+                        continue;
+                    double d[3];
+                    cell_offset(cfg, &P[p], x[0], x[1], x[2], d);
+                    double ds = particle_sdf_at(&P[p], d);
+                    if (ds >= 0.5 * cfg->eps) continue;
+                    double Bp = orc_indicator(ds, cfg->eps), up[3];
+                    rigid_velocity(&P[p], d, up);
+                    long xs = cell_index(cfg, x[0], x[1], x[2]);
+                    S0[xs] += Bp;
+                    for (int k = 0; k < 3; ++k) S1[k * N + xs] += Bp * up[k];
+                }
+    }
+    for (long x = 0; x < N; ++x) {
+        B[x] = S0[x] < 1.0 ? S0[x] : 1.0;
+        for (int k = 0; k < 3; ++k) us[k * N + x] = S0[x] > 0.0 ? S1[k * N + x] / S0[x] : 0.0;
+    }
+    free(S0);
+    free(S1);
+}
+
+/* ---------------------------------------------------------------------------
+ * One time step in the order of the paper's time-step algorithm (Sec. 4.2):
+ * MEA -> external force -> equations of motion -> EDM coupling -> collide ->
+ * stream.  The communication and assignment steps have nothing to do on one
+ * address space.  F_last/T_last receive the hydrodynamic force and torque of
+ * the last MEA.  Returns 0.
+ * ------------------------------------------------------------------------- */
+int orc_run(const ocfg *cfg, int np, opart *P, double *f, int nsteps, double *Flast, double *Tlast) {
+    init_tables();
+    long N = orc_ncells(cfg);
+    double *fs = (double *)malloc(sizeof(double) * Q * (size_t)N);
+    double *B = (double *)malloc(sizeof(double) * (size_t)N);
+    double *us = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    double *F = (double *)calloc((size_t)(np > 0 ? np : 1) * 3, sizeof(double));
+    double *T = (double *)calloc((size_t)(np > 0 ? np : 1) * 3, sizeof(double));
+    for (int s = 0; s < nsteps; ++s) {
+        orc_mea(cfg, np, P, f, F, T);
+        orc_apply_eom(cfg, np, P, F, T);
+        orc_coupling(cfg, np, P, B, us);
+        orc_collide(cfg, f, B, us, fs);
+        orc_stream(cfg, fs, f);
+    }
+    if (Flast && nsteps > 0) memcpy(Flast, F, sizeof(double) * 3 * np);
+    if (Tlast && nsteps > 0) memcpy(Tlast, T, sizeof(double) * 3 * np);
+    free(fs); free(B); free(us); free(F); free(T);
+    return 0;
+}
+
+/* Reported fields: bare rho and u, the EDM physical velocity
+ * u_phys = u + du/2 with du from the current particles, and B. */
+void orc_fields(const ocfg *cfg, int np, const opart *P, const double *f, double *rho, double *u,
+                double *uphys, double *B) {
+    long N = orc_ncells(cfg);
+    double *Bt = (double *)malloc(sizeof(double) * (size_t)N);
+    double *us = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    orc_moments(cfg, f, rho, u);
+    orc_coupling(cfg, np, P, Bt, us);
+    for (long x = 0; x < N; ++x) {
+        for (int k = 0; k < 3; ++k) {
+            double du = Bt[x] * (us[k * N + x] - u[k * N + x]) + (1.0 - Bt[x]) * cfg->af[k];
+            uphys[k * N + x] = u[k * N + x] + 0.5 * du;
+        }
+        if (B) B[x] = Bt[x];
+    }
+    free(Bt);
+    free(us);
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

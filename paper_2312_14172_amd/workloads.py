@@ -1,0 +1,317 @@
+"""Seeded synthetic inputs for the HLBM step: lattice configurations, particle
+lists and initial fields.
+
+This module generates inputs only.  It holds none of the method's arithmetic
+(no populations, indicator, momentum exchange or equations of motion) and is
+the single piece of code shared by the HIP path's tests/benchmarks and the
+CPU oracle's tests.  Shapes, sizes and distributions follow the paper's
+hindered-settling workload (Sec. 5.1: resolved spheres of 12-27 cells per
+diameter, solid fractions 0.05-0.3, tau = 0.55) scaled to the five workloads
+below; every random draw comes from ``numpy.random.default_rng(seed)``.
+
+Particle records use ``PARTICLE_DTYPE`` (field names, not byte layout, are the
+contract: each binding copies them into its own record).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SPHERE, ROUNDED_CUBE, SPHEROID = 0, 1, 2
+SHAPE_NAMES = {SPHERE: "sphere", ROUNDED_CUBE: "rounded_cube", SPHEROID: "spheroid"}
+
+PARTICLE_DTYPE = np.dtype([
+    ("pos", "<f8", 3), ("quat", "<f8", 4), ("vel", "<f8", 3), ("omega", "<f8", 3),
+    ("mass", "<f8"), ("volume", "<f8"), ("inertia", "<f8", 3), ("param", "<f8", 3),
+    ("shape", "<i4"), ("flags", "<i4")])
+
+
+# ---------------------------------------------------------------------------
+# Shape geometry of the inputs: volume, mass, principal inertia, circumradius
+# ---------------------------------------------------------------------------
+def _gauss_legendre(n, a, b):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (b - a) * x + 0.5 * (b + a), 0.5 * (b - a) * w
+
+
+def rounded_cube_moments(h: float, rc: float):
+    """Volume and I_zz/mass-density of the Minkowski sum of a cube of
+    half-extent b = h - rc with a ball of radius rc (unit density).
+
+    Integrated slice by slice: at height z the cross-section is a square of
+    half-side b with corners rounded to radius rho(z) (rho = rc in the core,
+    sqrt(rc^2 - s^2) at distance s above it)."""
+    b = h - rc
+
+    def area(rho):
+        return 4 * b * b + 8 * b * rho + math.pi * rho * rho
+
+    def polar(rho):  # integral of x^2 + y^2 over the rounded square
+        core = 8 * b ** 4 / 3
+        sides = 4 * (2 * b * ((b + rho) ** 3 - b ** 3) / 3 + 2 * b ** 3 * rho / 3)
+        corners = 4 * (math.pi * b * b * rho * rho / 2 + 4 * b * rho ** 3 / 3
+                       + math.pi * rho ** 4 / 8)
+        return core + sides + corners
+
+    phi, w = _gauss_legendre(64, 0.0, 0.5 * math.pi)
+    rho = rc * np.cos(phi)
+    jac = rc * np.cos(phi)
+    vol = 2 * b * area(rc) + 2 * float(np.sum(w * jac * area(rho)))
+    izz = 2 * b * polar(rc) + 2 * float(np.sum(w * jac * polar(rho)))
+    return vol, izz
+
+
+def shape_volume(shape: int, prm) -> float:
+    if shape == SPHERE:
+        return 4.0 / 3.0 * math.pi * prm[0] ** 3
+    if shape == ROUNDED_CUBE:
+        return rounded_cube_moments(prm[0], prm[1])[0]
+    if shape == SPHEROID:
+        return 4.0 / 3.0 * math.pi * prm[0] * prm[1] * prm[1]
+    raise ValueError(shape)
+
+
+def shape_inertia(shape: int, prm, mass: float):
+    if shape == SPHERE:
+        v = 0.4 * mass * prm[0] ** 2
+        return (v, v, v)
+    if shape == ROUNDED_CUBE:
+        vol, izz = rounded_cube_moments(prm[0], prm[1])
+        v = mass / vol * izz
+        return (v, v, v)
+    if shape == SPHEROID:  # symmetry axis = body x
+        a, b = prm[0], prm[1]
+        return (0.4 * mass * b * b, 0.2 * mass * (a * a + b * b), 0.2 * mass * (a * a + b * b))
+    raise ValueError(shape)
+
+
+def circumradius(shape: int, prm) -> float:
+    if shape == SPHERE:
+        return float(prm[0])
+    if shape == ROUNDED_CUBE:
+        return math.sqrt(3.0) * (prm[0] - prm[1]) + prm[1]
+    if shape == SPHEROID:
+        return float(max(prm[0], prm[1]))
+    raise ValueError(shape)
+
+
+def equal_volume_params(shape: int, r_eq: float):
+    """Shape parameters with the volume of a sphere of radius r_eq:
+    rounded cube with corner radius 0.2 h, prolate 2:1 spheroid."""
+    if shape == SPHERE:
+        return (r_eq, 0.0, 0.0)
+    if shape == ROUNDED_CUBE:
+        v_target = 4.0 / 3.0 * math.pi * r_eq ** 3
+        unit = rounded_cube_moments(1.0, 0.2)[0]
+        h = (v_target / unit) ** (1.0 / 3.0)
+        return (h, 0.2 * h, 0.0)
+    if shape == SPHEROID:
+        b = r_eq / 2 ** (1.0 / 3.0)
+        return (2 * b, b, 0.0)
+    raise ValueError(shape)
+
+
+def make_particle(shape: int, prm, pos, quat=(1.0, 0.0, 0.0, 0.0), density_ratio=2.0,
+                  rho_f=1.0, vel=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0), fixed=False):
+    rec = np.zeros((), dtype=PARTICLE_DTYPE)
+    prm = tuple(float(v) for v in prm) + (0.0,) * (3 - len(prm))
+    vol = shape_volume(shape, prm)
+    mass = density_ratio * rho_f * vol
+    rec["pos"] = pos
+    rec["quat"] = quat
+    rec["vel"] = vel
+    rec["omega"] = omega
+    rec["volume"] = vol
+    rec["inertia"] = shape_inertia(shape, prm, mass)
+    rec["mass"] = -1.0 if fixed else mass
+    rec["param"] = prm
+    rec["shape"] = shape
+    return rec
+
+
+def shoemake_quaternion(rng: np.random.Generator):
+    """Uniformly random unit quaternion (Shoemake, Graphics Gems III, 1992)."""
+    u1, u2, u3 = rng.random(3)
+    a, b = math.sqrt(1 - u1), math.sqrt(u1)
+    return (b * math.cos(2 * math.pi * u3), a * math.sin(2 * math.pi * u2),
+            a * math.cos(2 * math.pi * u2), b * math.sin(2 * math.pi * u3))
+
+
+# ---------------------------------------------------------------------------
+# Random sequential addition on circumspheres
+# ---------------------------------------------------------------------------
+def rsa_positions(rng, radii, n, bc, gap=1.0, wall_margin=1.0, batch=512, max_batches=20000):
+    """Place spheres of the given radii (in the given order) uniformly at
+    random without overlap: centre distance >= r_i + r_j + gap, minimum image
+    on periodic axes, and at least r + wall_margin from a wall."""
+    n = np.asarray(n, dtype=np.float64)
+    bc = np.asarray(bc)
+    pos = np.zeros((len(radii), 3))
+    placed = 0
+    batches = 0
+    while placed < len(radii):
+        r = radii[placed]
+        lo = np.where(bc == 1, r + wall_margin, 0.0)
+        hi = np.where(bc == 1, n - r - wall_margin, n)
+        cand = lo + (hi - lo) * rng.random((batch, 3))
+        if placed:
+            d = cand[:, None, :] - pos[None, :placed, :]
+            per = bc == 0
+            d[..., per] -= n[per] * np.round(d[..., per] / n[per])
+            dist = np.sqrt(np.sum(d * d, axis=-1))
+            ok = np.all(dist >= radii[None, :placed] + r + gap, axis=1)
+        else:
+            ok = np.ones(batch, dtype=bool)
+        idx = np.flatnonzero(ok)
+        if idx.size:
+            pos[placed] = cand[idx[0]]
+            placed += 1
+        else:
+            batches += 1
+            if batches > max_batches:
+                raise RuntimeError(f"RSA stalled after placing {placed} of {len(radii)}")
+    return pos
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    n: tuple
+    bc: tuple
+    tau: float
+    steps: int
+    precision: str
+    gravity: tuple = (0.0, 0.0, -1e-5)
+    density_ratio: float = 2.0
+    eps: float = 0.5
+    rho_f: float = 1.0
+    fluid_accel: tuple = (0.0, 0.0, 0.0)
+    seed: int = 0
+    description: str = ""
+    learned: bool = False
+    particles: np.ndarray = field(default=None, repr=False)
+
+    @property
+    def ncells(self):
+        return self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def solid_fraction(self):
+        return float(np.sum(self.particles["volume"]) / self.ncells) if len(self.particles) else 0.0
+
+
+def single_sphere(n=32, r=4.0, tau=0.8, steps=100, precision="fp64"):
+    """One sphere of radius 4 centred on the corner shared by eight cells at the
+    box centre, periodic 32^3, tau = 0.8, density ratio 2, g = 1e-5."""
+    w = Workload("sphere32", (n, n, n), (0, 0, 0), tau, steps, precision, seed=1,
+                 description="32^3 periodic, one sphere r=4 at the box centre, tau=0.8")
+    w.particles = np.array([make_particle(SPHERE, (r,), (n / 2, n / 2, n / 2), density_ratio=2.0)])
+    return w
+
+
+def settling_spheres(n=128, count=200, seed=2, tau=0.6, steps=1000, precision="fp32"):
+    """Spheres with radius U[5,7] placed by RSA (gap >= 1) in a box periodic in
+    x, y with half-way walls at z = 0 and z = n; tau = 0.6; density ratio 2."""
+    rng = np.random.default_rng(seed)
+    radii = rng.uniform(5.0, 7.0, count)
+    order = np.argsort(-radii, kind="stable")
+    pos = rsa_positions(rng, radii[order], (n, n, n), (0, 0, 1))
+    recs = []
+    for k, i in enumerate(order):
+        recs.append(make_particle(SPHERE, (radii[i],), pos[k], density_ratio=2.0))
+    w = Workload(f"spheres{n}", (n, n, n), (0, 0, 1), tau, steps, precision, seed=seed,
+                 description=f"{n}^3, z walls, {count} spheres r~U[5,7], tau={tau}")
+    w.particles = np.array(recs)
+    return w
+
+
+def mixed_shapes(n=256, count=2000, r_eq=6.0, seed=3, tau=0.6, steps=1000, precision="fp16s",
+                 learned=False, density_ratio=2.0, r_eq_range=None, gap=1.0):
+    """Spheres, rounded cubes (corner radius 0.2 h) and prolate 2:1 spheroids in
+    equal thirds, equal volume r_eq (or r_eq ~ U[r_eq_range]), uniformly random
+    orientations, RSA on circumspheres, z walls."""
+    rng = np.random.default_rng(seed)
+    shapes = np.array([SPHERE, ROUNDED_CUBE, SPHEROID] * (count // 3 + 1))[:count]
+    if r_eq_range is None:
+        req = np.full(count, float(r_eq))
+    else:
+        req = rng.uniform(r_eq_range[0], r_eq_range[1], count)
+    prms = [equal_volume_params(int(s), float(r)) for s, r in zip(shapes, req)]
+    rcirc = np.array([circumradius(int(s), p) for s, p in zip(shapes, prms)])
+    quats = [shoemake_quaternion(rng) for _ in range(count)]
+    order = np.argsort(-rcirc, kind="stable")
+    pos = rsa_positions(rng, rcirc[order], (n, n, n), (0, 0, 1), gap=gap)
+    recs = []
+    for k, i in enumerate(order):
+        recs.append(make_particle(int(shapes[i]), prms[i], pos[k], quat=quats[i],
+                                  density_ratio=density_ratio))
+    w = Workload(f"mixed{n}", (n, n, n), (0, 0, 1), tau, steps, precision, seed=seed,
+                 density_ratio=density_ratio, learned=learned,
+                 description=f"{n}^3, z walls, {count} mixed shapes r_eq={r_eq}, tau={tau}")
+    w.particles = np.array(recs)
+    return w
+
+
+def smooth_fields(n, seed, rho_amp=1e-3, u_amp=1e-2, modes=3):
+    """Smooth periodic random density and velocity fields (sums of a few
+    Fourier modes with seeded amplitudes and phases).  Returns rho[N], u[3,N]
+    in cell order x + nx*(y + ny*z)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = n
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5,
+                          indexing="ij")
+
+    def field1():
+        acc = np.zeros_like(x)
+        for _ in range(modes):
+            k = rng.integers(0, 3, 3)
+            ph = rng.random() * 2 * math.pi
+            a = rng.normal()
+            acc += a * np.sin(2 * math.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz) + ph)
+        return acc / modes
+
+    rho = 1.0 + rho_amp * field1()
+    u = np.stack([u_amp * field1() for _ in range(3)])
+    return rho.reshape(-1).copy(), u.reshape(3, -1).copy()
+
+
+def random_particles_small(n, count, seed, shapes=(SPHERE, ROUNDED_CUBE, SPHEROID), r_eq=(2.5, 4.0),
+                           bc=(0, 0, 1), moving=True, density_ratio=2.0, gap=0.5):
+    """A few mixed particles for small parity lattices: random shapes, sizes,
+    orientations and (optionally) velocities and angular velocities."""
+    rng = np.random.default_rng(seed)
+    sh = [shapes[i % len(shapes)] for i in range(count)]
+    req = rng.uniform(r_eq[0], r_eq[1], count)
+    prms = [equal_volume_params(int(s), float(r)) for s, r in zip(sh, req)]
+    rcirc = np.array([circumradius(int(s), p) for s, p in zip(sh, prms)])
+    pos = rsa_positions(rng, rcirc, n, bc, gap=gap, wall_margin=1.5)
+    recs = []
+    for i in range(count):
+        vel = tuple(rng.uniform(-0.01, 0.01, 3)) if moving else (0.0, 0.0, 0.0)
+        om = tuple(rng.uniform(-0.004, 0.004, 3)) if moving else (0.0, 0.0, 0.0)
+        recs.append(make_particle(int(sh[i]), prms[i], pos[i], quat=shoemake_quaternion(rng),
+                                  vel=vel, omega=om, density_ratio=density_ratio))
+    return np.array(recs)
+
+
+def get(name: str, **kw) -> Workload:
+    """Named workloads:
+    sphere32   -- 32^3 periodic, one sphere (parity case);
+    spheres128 -- 128^3, z walls, 200 spheres r~U[5,7], tau 0.6;
+    mixed256   -- 256^3, z walls, 2000 mixed shapes r_eq 6, tau 0.6;
+    mixed256_learned -- as mixed256 with the learned indicator for non-spheres.
+    """
+    if name == "sphere32":
+        return single_sphere(**kw)
+    if name == "spheres128":
+        return settling_spheres(**kw)
+    if name == "mixed256":
+        return mixed_shapes(**kw)
+    if name == "mixed256_learned":
+        return mixed_shapes(learned=True, **kw)
+    raise KeyError(name)
