@@ -1,0 +1,167 @@
+/*
+ * hlbm.h -- C ABI of the MI355X (gfx950) HLBM hot path.
+ *
+ * The library advances a D3Q19 BGK lattice Boltzmann fluid coupled to resolved
+ * rigid particles with the homogenized lattice Boltzmann method (HLBM) of
+ * Marquardt, Hafen and Krause, "A novel particle decomposition scheme to
+ * improve parallel performance of fully resolved particulate flow
+ * simulations" (arXiv 2312.14172):
+ *   - fluid: D3Q19 velocity set, BGK collision, streaming with dt = dx = 1
+ *     (Sec. 3.1, collide/stream/BGK/relaxation/equilibrium equations);
+ *   - particle -> fluid: trigonometric indicator B(d_s) of the signed
+ *     distance, velocity difference du = B (u_p(x) - u_f) and the
+ *     exact-difference source S_i = feq(rho, u + du) - feq(rho, u)
+ *     (Sec. 3.2, level-set, velocity-difference and source equations);
+ *   - fluid -> particle: momentum exchange summed over the cells whose centre
+ *     is inside the particle, force and torque (Sec. 3.2, MEA, force and
+ *     torque equations);
+ *   - Newton-Euler equations with gravity and buoyancy (Sec. 2.2, Sec. 5.1);
+ *   - in the order of the paper's time-step algorithm (Sec. 4.2); its
+ *     communication and assignment steps have nothing to do on one GPU.
+ *
+ * Units are lattice units throughout.  Cell (x, y, z) has its centre at
+ * (x + 1/2, y + 1/2, z + 1/2); cell index = x + nx * (y + ny * z).
+ *
+ * Conventions for every call:
+ *   - return 0 on success or a negative HLBM_E* code; hlbm_last_error()
+ *     returns a message for the calling thread's last failure;
+ *   - no C++ exception crosses this ABI;
+ *   - the caller owns every buffer it passes; the library keeps no pointer to
+ *     a caller buffer after the call returns, except the device workspace
+ *     handed to hlbm_init, which must stay allocated until hlbm_destroy;
+ *   - the library allocates no device memory; everything lives in the
+ *     caller's workspace;
+ *   - all device work is queued on cfg.stream (NULL = the default stream);
+ *     calls that return data synchronise that stream and report any error a
+ *     kernel raised since the last such call;
+ *   - a context is used by one host thread at a time.
+ */
+#ifndef HLBM_H
+#define HLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define HLBM_OK 0
+#define HLBM_EINVAL (-1)       /* bad argument or configuration */
+#define HLBM_ENOMEM (-2)       /* workspace too small */
+#define HLBM_EDEVICE (-3)      /* a HIP call failed */
+#define HLBM_ESTATE (-4)       /* call not valid in the current state */
+#define HLBM_EUNSTABLE (-5)    /* non-finite / non-positive density, |u| > 0.3, or a
+                                  particle left the domain through a wall */
+#define HLBM_EUNSUPPORTED (-6) /* a capacity of the library was exceeded */
+
+/* boundary type per axis */
+#define HLBM_BC_PERIODIC 0
+#define HLBM_BC_WALL 1 /* resting half-way bounce-back walls at 0 and n */
+
+/* population storage / arithmetic */
+#define HLBM_FP64 0  /* FP64 storage and arithmetic */
+#define HLBM_FP32 1  /* FP32 arithmetic, FP32 storage of f_i - w_i */
+#define HLBM_FP16S 2 /* FP32 arithmetic, FP16 storage of 256 (f_i - w_i) / w_i */
+
+/* particle shapes (body-frame parameters in hlbm_particle.param) */
+#define HLBM_SPHERE 0       /* param[0] = radius */
+#define HLBM_ROUNDED_CUBE 1 /* param[0] = half-extent h, param[1] = corner radius
+                               (cube of half-extent h - r_c dilated by r_c) */
+#define HLBM_SPHEROID 2     /* param[0] = semi-axis a along body x,
+                               param[1] = the two equal semi-axes */
+
+/* field selection for hlbm_get_fields */
+#define HLBM_FIELD_RHO 1u    /* rho = sum_i f_i                              (1 plane) */
+#define HLBM_FIELD_U 2u      /* bare u = sum_i c_i f_i / rho                 (3 planes) */
+#define HLBM_FIELD_U_PHYS 4u /* u + du/2 with du from the current particles  (3 planes) */
+#define HLBM_FIELD_SOLID 8u  /* B = min(1, sum_p B_p)                        (1 plane) */
+
+typedef struct hlbm_config {
+    int32_t nx, ny, nz;   /* lattice size, each >= 1 */
+    int32_t bc[3];        /* HLBM_BC_* per axis */
+    int32_t precision;    /* HLBM_FP64 | HLBM_FP32 | HLBM_FP16S */
+    int32_t max_particles;/* capacity, >= 0 */
+    double tau;           /* BGK relaxation time > 1/2; nu = (tau - 1/2) / 3 */
+    double eps;           /* indicator smoothing width (the paper uses 1/2), > 0 */
+    double rho_f;         /* fluid density used in the buoyancy term */
+    double gravity[3];    /* gravity vector g (e.g. {0, 0, -1e-5}) */
+    double fluid_accel[3];/* body acceleration of the fluid outside the solid */
+    void *stream;         /* hipStream_t, NULL = default stream */
+} hlbm_config;
+
+typedef struct hlbm_particle {
+    double pos[3];     /* centre of mass */
+    double quat[4];    /* unit quaternion (w, x, y, z), body -> world */
+    double vel[3];     /* velocity of the centre of mass */
+    double omega[3];   /* angular velocity, world frame */
+    double mass;       /* > 0; <= 0 holds the particle fixed at its state */
+    double volume;     /* volume used for buoyancy */
+    double inertia[3]; /* principal moments of inertia in the body frame, > 0 */
+    double param[3];   /* shape parameters, see HLBM_SPHERE etc. */
+    int32_t shape;     /* HLBM_SPHERE | HLBM_ROUNDED_CUBE | HLBM_SPHEROID */
+    int32_t flags;     /* reserved, must be 0 */
+} hlbm_particle;
+
+typedef struct hlbm_ctx hlbm_ctx;
+
+/* Bytes of device workspace hlbm_init needs for cfg (two population buffers,
+ * particle records, tile lists, partial-force records and a staging area of
+ * 4 doubles per cell for field transfers).  Returns HLBM_EINVAL for an
+ * invalid configuration. */
+int hlbm_workspace_size(const hlbm_config *cfg, size_t *bytes);
+
+/* Create a context over a device workspace of at least hlbm_workspace_size
+ * bytes (any alignment; 256-byte alignment is used internally).  The fluid
+ * starts at rest (f_i = w_i, Sec. 3.1 weights), with no particles.  The
+ * configuration is copied.  On failure *out is NULL. */
+int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx **out);
+
+/* Release the host-side context; the workspace is the caller's to free. */
+int hlbm_destroy(hlbm_ctx *ctx);
+
+/* Replace the particle set with n host records (copied).  The records are
+ * the particle data of Sec. 4.1 (position, orientation, velocity, angular
+ * velocity, shape).  Checks: n <= max_particles; finite values; unit
+ * quaternion (|q| within 1e-6 of 1, renormalised); inertia > 0; positive
+ * shape parameters; a particle's reach (circumradius + 2) below half of
+ * every periodic extent; centres inside the domain on wall axes. */
+int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host);
+
+/* Set the fluid to equilibrium f_i = feq_i(rho, u) (Sec. 3.1) from host
+ * arrays rho[ncells] and u[3][ncells] (x-fastest planes); rho == NULL means
+ * rho = 1 and u == NULL means u = 0. */
+int hlbm_set_fields(hlbm_ctx *ctx, const double *rho, const double *u);
+
+/* Queue nsteps >= 0 time steps on the stream.  Each step: momentum exchange
+ * force and torque on every particle (Sec. 3.2) -> gravity and buoyancy ->
+ * Newton-Euler update in FP64 -> particle-to-lattice coupling with the
+ * updated particles -> fused collide and stream with the exact-difference
+ * source.  Asynchronous: errors raised inside kernels are reported by the
+ * next hlbm_get_* call. */
+int hlbm_step(hlbm_ctx *ctx, int32_t nsteps);
+
+/* Copy to host the hydrodynamic force F[n][3] and torque T[n][3] on each
+ * particle from the last completed step's momentum exchange (zero before the
+ * first step), and optionally the current particle records.  Any pointer may
+ * be NULL.  Synchronises the stream. */
+int hlbm_get_forces(hlbm_ctx *ctx, double *F, double *T, hlbm_particle *state);
+
+/* Write the fields selected by mask, as FP64 planes of ncells values each,
+ * in the order rho, u (3), u_phys (3), B, to out (host memory if
+ * out_on_device == 0, else device memory on the context's device).  The
+ * fields are those of the current state (post-streaming populations at the
+ * current integer time and the current particles).  Synchronises the stream. */
+int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_device);
+
+/* Number of particles currently held. */
+int hlbm_num_particles(const hlbm_ctx *ctx, int32_t *n);
+
+/* Message for the calling thread's most recent failure ("" if none). */
+const char *hlbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HLBM_H */

@@ -1,0 +1,385 @@
+// hlbm_api.hip -- the C ABI declared in include/hlbm.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include <string>
+#include <vector>
+
+#include "hlbm_internal.h"
+
+using namespace hlbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(HLBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t pop_bytes(int precision) { return precision == HLBM_FP64 ? 8 : (precision == HLBM_FP32 ? 4 : 2); }
+
+struct Layout {
+  size_t fA, fB, parts, stage_parts, tcnt, tlist, partial, status, stage, total;
+};
+
+int validate(const hlbm_config *c) {
+  if (!c) return fail(HLBM_EINVAL, "config is NULL");
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(HLBM_EINVAL, "lattice size must be >= 1");
+  const long long N = (long long)c->nx * c->ny * c->nz;
+  if (N * 19 >= (1LL << 40)) return fail(HLBM_EINVAL, "lattice too large");
+  for (int k = 0; k < 3; ++k)
+    if (c->bc[k] != HLBM_BC_PERIODIC && c->bc[k] != HLBM_BC_WALL)
+      return fail(HLBM_EINVAL, "bc[%d] must be HLBM_BC_PERIODIC or HLBM_BC_WALL", k);
+  if (c->precision < HLBM_FP64 || c->precision > HLBM_FP16S) return fail(HLBM_EINVAL, "unknown precision");
+  if (c->max_particles < 0) return fail(HLBM_EINVAL, "max_particles < 0");
+  if (!(c->tau > 0.5) || !isfinite(c->tau)) return fail(HLBM_EINVAL, "tau must be > 1/2 (nu > 0)");
+  if (!(c->eps > 0.0) || !isfinite(c->eps)) return fail(HLBM_EINVAL, "eps must be > 0");
+  if (!isfinite(c->rho_f)) return fail(HLBM_EINVAL, "rho_f not finite");
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(c->gravity[k]) || !isfinite(c->fluid_accel[k]))
+      return fail(HLBM_EINVAL, "gravity / fluid_accel not finite");
+  return HLBM_OK;
+}
+
+Lattice make_lattice(const hlbm_config *c) {
+  Lattice L;
+  L.nx = c->nx; L.ny = c->ny; L.nz = c->nz;
+  for (int k = 0; k < 3; ++k) L.bc[k] = c->bc[k];
+  L.ntx = (c->nx + TX - 1) / TX;
+  L.nty = (c->ny + TY - 1) / TY;
+  L.ntz = (c->nz + TZ - 1) / TZ;
+  L.ntiles = L.ntx * L.nty * L.ntz;
+  L.N = (long long)c->nx * c->ny * c->nz;
+  L.omega = 1.0 / c->tau;
+  L.eps = c->eps;
+  for (int k = 0; k < 3; ++k) { L.af[k] = c->fluid_accel[k]; L.g[k] = c->gravity[k]; }
+  L.rho_f = c->rho_f;
+  return L;
+}
+
+Layout make_layout(const hlbm_config *c, const Lattice &L) {
+  Layout y;
+  size_t off = 0;
+  const size_t pop = align_up((size_t)19 * L.N * pop_bytes(c->precision));
+  const size_t np = c->max_particles > 0 ? (size_t)c->max_particles : 1;
+  y.fA = off; off += pop;
+  y.fB = off; off += pop;
+  y.parts = off; off += align_up(np * sizeof(DevParticle));
+  y.stage_parts = off; off += align_up(np * sizeof(hlbm_particle));
+  y.tcnt = off; off += align_up((size_t)L.ntiles * sizeof(int));
+  y.tlist = off; off += align_up((size_t)L.ntiles * MAXC * sizeof(int));
+  y.partial = off; off += align_up((size_t)L.ntiles * MAXC * 6 * sizeof(double));
+  y.status = off; off += 256;
+  y.stage = off; off += align_up((size_t)4 * L.N * sizeof(double));
+  y.total = off + 256;  // slack for aligning the caller's base pointer
+  return y;
+}
+
+}  // namespace
+
+struct hlbm_ctx {
+  hlbm_config cfg;
+  Lattice L;
+  Layout lay;
+  hipStream_t stream;
+  char *base;
+  void *fA, *fB;
+  DevParticle *parts;
+  hlbm_particle *stage_parts;
+  int *tcnt, *tlist, *status;
+  double *partial, *stage;
+  int n;
+  bool binned;        // tile lists describe the current particles
+  bool forces_ready;  // partial records hold the momentum exchange of the current state
+  long long steps_done;
+};
+
+namespace {
+
+int check_status(hlbm_ctx *c) {
+  int st = 0;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (st) {
+    const int zero = 0;
+    HIP_TRY(hipMemcpy(c->status, &zero, sizeof(int), hipMemcpyHostToDevice));
+    if (st & ST_TILE_OVERFLOW)
+      return fail(HLBM_EUNSUPPORTED, "more than %d particles touch one 64x4x4 tile", MAXC);
+    if (st & ST_WALL_EXIT) return fail(HLBM_EUNSTABLE, "a particle centre left the domain through a wall");
+    return fail(HLBM_EUNSTABLE, "non-finite or non-positive density, or |u| > 0.3");
+  }
+  return HLBM_OK;
+}
+
+int rebin(hlbm_ctx *c) {
+  HIP_TRY(launch_fill_int(c->tcnt, 0, c->L.ntiles, c->stream));
+  HIP_TRY(launch_bin(c->L, c->parts, c->n, c->tcnt, c->tlist, c->status, c->stream));
+  c->binned = true;
+  return HLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hlbm_last_error(void) { return g_last_error.c_str(); }
+
+int hlbm_workspace_size(const hlbm_config *cfg, size_t *bytes) {
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!bytes) return fail(HLBM_EINVAL, "bytes is NULL");
+  const Lattice L = make_lattice(cfg);
+  *bytes = make_layout(cfg, L).total;
+  return HLBM_OK;
+}
+
+int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx **out) {
+  if (!out) return fail(HLBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!d_workspace) return fail(HLBM_EINVAL, "workspace is NULL");
+  const Lattice L = make_lattice(cfg);
+  const Layout lay = make_layout(cfg, L);
+  if (bytes < lay.total) return fail(HLBM_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, lay.total);
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, d_workspace) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(HLBM_EINVAL, "workspace is not device memory");
+  }
+  hlbm_ctx *c = new (std::nothrow) hlbm_ctx();
+  if (!c) return fail(HLBM_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  c->L = L;
+  c->lay = lay;
+  c->stream = (hipStream_t)cfg->stream;
+  c->base = (char *)(((uintptr_t)d_workspace + 255) & ~(uintptr_t)255);
+  c->fA = c->base + lay.fA;
+  c->fB = c->base + lay.fB;
+  c->parts = (DevParticle *)(c->base + lay.parts);
+  c->stage_parts = (hlbm_particle *)(c->base + lay.stage_parts);
+  c->tcnt = (int *)(c->base + lay.tcnt);
+  c->tlist = (int *)(c->base + lay.tlist);
+  c->partial = (double *)(c->base + lay.partial);
+  c->status = (int *)(c->base + lay.status);
+  c->stage = (double *)(c->base + lay.stage);
+  c->n = 0;
+  c->binned = false;
+  c->forces_ready = false;
+  c->steps_done = 0;
+  // rest state: every deviation f_i - w_i is zero
+  hipError_t e = hipMemsetAsync(c->fA, 0, (size_t)19 * L.N * pop_bytes(cfg->precision), c->stream);
+  if (e == hipSuccess) e = launch_fill_int(c->tcnt, 0, L.ntiles, c->stream);
+  if (e == hipSuccess) e = launch_fill_int(c->status, 0, 1, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(HLBM_EDEVICE, "initialisation failed: %s", hipGetErrorString(e));
+  }
+  c->binned = true;
+  *out = c;
+  return HLBM_OK;
+}
+
+int hlbm_destroy(hlbm_ctx *ctx) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return HLBM_OK;
+}
+
+int hlbm_num_particles(const hlbm_ctx *ctx, int32_t *n) {
+  if (!ctx || !n) return fail(HLBM_EINVAL, "NULL argument");
+  *n = ctx->n;
+  return HLBM_OK;
+}
+
+int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  if (n < 0 || n > ctx->cfg.max_particles)
+    return fail(HLBM_EINVAL, "n = %d outside [0, max_particles = %d]", n, ctx->cfg.max_particles);
+  if (n > 0 && !host) return fail(HLBM_EINVAL, "particles is NULL");
+  const int nn[3] = {ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.nz};
+  for (int i = 0; i < n; ++i) {
+    const hlbm_particle &p = host[i];
+    const double *vals[] = {p.pos, p.quat, p.vel, p.omega, p.inertia, p.param};
+    const int lens[] = {3, 4, 3, 3, 3, 3};
+    for (int a = 0; a < 6; ++a)
+      for (int k = 0; k < lens[a]; ++k)
+        if (!isfinite(vals[a][k])) return fail(HLBM_EINVAL, "particle %d: non-finite value", i);
+    if (!isfinite(p.mass) || !isfinite(p.volume)) return fail(HLBM_EINVAL, "particle %d: non-finite mass", i);
+    if (p.shape < HLBM_SPHERE || p.shape > HLBM_SPHEROID) return fail(HLBM_EINVAL, "particle %d: bad shape", i);
+    if (p.flags != 0) return fail(HLBM_EINVAL, "particle %d: flags must be 0", i);
+    const double qn = sqrt(p.quat[0] * p.quat[0] + p.quat[1] * p.quat[1] + p.quat[2] * p.quat[2] +
+                           p.quat[3] * p.quat[3]);
+    if (fabs(qn - 1.0) > 1e-6) return fail(HLBM_EINVAL, "particle %d: quaternion not unit", i);
+    if (p.mass > 0 && !(p.inertia[0] > 0 && p.inertia[1] > 0 && p.inertia[2] > 0))
+      return fail(HLBM_EINVAL, "particle %d: inertia must be > 0", i);
+    double rc;
+    if (p.shape == HLBM_SPHERE) {
+      if (!(p.param[0] > 0)) return fail(HLBM_EINVAL, "particle %d: radius must be > 0", i);
+      rc = p.param[0];
+    } else if (p.shape == HLBM_ROUNDED_CUBE) {
+      if (!(p.param[0] > 0 && p.param[1] >= 0 && p.param[1] <= p.param[0]))
+        return fail(HLBM_EINVAL, "particle %d: need h > 0 and 0 <= r_c <= h", i);
+      rc = sqrt(3.0) * (p.param[0] - p.param[1]) + p.param[1];
+    } else {
+      if (!(p.param[0] > 0 && p.param[1] > 0)) return fail(HLBM_EINVAL, "particle %d: semi-axes must be > 0", i);
+      rc = fmax(p.param[0], p.param[1]);
+    }
+    const double reach = rc + fmax(0.5 * ctx->cfg.eps, sqrt(2.0)) + 1.0;
+    for (int k = 0; k < 3; ++k) {
+      if (ctx->cfg.bc[k] == HLBM_BC_PERIODIC && 2.0 * reach >= nn[k])
+        return fail(HLBM_EINVAL, "particle %d: reach %.3f not below half of periodic extent %d", i, reach, nn[k]);
+      if (ctx->cfg.bc[k] == HLBM_BC_WALL && !(p.pos[k] >= 0 && p.pos[k] <= nn[k]))
+        return fail(HLBM_EINVAL, "particle %d: centre outside the walls", i);
+    }
+    // a reach box spans at most 2 reach + 1 cells: 16 tiles of 4 cells per axis
+    if (reach > 28.0) return fail(HLBM_EUNSUPPORTED, "particle %d: circumradius above 25 cells", i);
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (n > 0) {
+    HIP_TRY(hipMemcpyAsync(ctx->stage_parts, host, sizeof(hlbm_particle) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(launch_prepare(ctx->L, ctx->stage_parts, ctx->parts, n, ctx->stream));
+  }
+  ctx->n = n;
+  ctx->forces_ready = false;
+  int rc = rebin(ctx);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return check_status(ctx);
+}
+
+int hlbm_set_fields(hlbm_ctx *ctx, const double *rho, const double *u) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  const long long N = ctx->L.N;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  const double *drho = nullptr, *du = nullptr;
+  if (rho) {
+    HIP_TRY(hipMemcpyAsync(ctx->stage, rho, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
+    drho = ctx->stage;
+  }
+  if (u) {
+    HIP_TRY(hipMemcpyAsync(ctx->stage + N, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice, ctx->stream));
+    du = ctx->stage + N;
+  }
+  HIP_TRY(launch_set_fields(ctx->cfg.precision, ctx->L, ctx->fA, drho, du, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->forces_ready = false;
+  return HLBM_OK;
+}
+
+int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  if (nsteps < 0) return fail(HLBM_EINVAL, "nsteps < 0");
+  const int prec = ctx->cfg.precision;
+  hipStream_t s = ctx->stream;
+  for (int it = 0; it < nsteps; ++it) {
+    if (ctx->n > 0) {
+      if (!ctx->binned) {
+        int rc = rebin(ctx);
+        if (rc) return rc;
+      }
+      if (!ctx->forces_ready) {
+        HIP_TRY(launch_mea_pull(prec, ctx->L, ctx->fA, ctx->parts, ctx->tcnt, ctx->tlist, ctx->partial, s));
+        ctx->forces_ready = true;
+      }
+      HIP_TRY(launch_eom(ctx->L, ctx->parts, ctx->n, ctx->tcnt, ctx->tlist, ctx->partial, ctx->status, s));
+      int rc = rebin(ctx);
+      if (rc) return rc;
+    }
+    HIP_TRY(launch_collide(prec, ctx->L, ctx->fA, ctx->fB, ctx->parts, ctx->tcnt, ctx->tlist, ctx->partial,
+                           ctx->status, s));
+    void *t = ctx->fA;
+    ctx->fA = ctx->fB;
+    ctx->fB = t;
+    ctx->forces_ready = ctx->n > 0;
+    ctx->steps_done++;
+  }
+  return HLBM_OK;
+}
+
+int hlbm_get_forces(hlbm_ctx *ctx, double *F, double *T, hlbm_particle *state) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  int rc = check_status(ctx);
+  if (rc) return rc;
+  if (ctx->n == 0) return HLBM_OK;
+  std::vector<DevParticle> p(ctx->n);
+  HIP_TRY(hipMemcpy(p.data(), ctx->parts, sizeof(DevParticle) * ctx->n, hipMemcpyDeviceToHost));
+  for (int i = 0; i < ctx->n; ++i) {
+    for (int k = 0; k < 3; ++k) {
+      if (F) F[3 * i + k] = p[i].Fh[k];
+      if (T) T[3 * i + k] = p[i].Th[k];
+    }
+    if (state) {
+      hlbm_particle &o = state[i];
+      for (int k = 0; k < 3; ++k) {
+        o.pos[k] = p[i].X[k]; o.vel[k] = p[i].U[k]; o.omega[k] = p[i].W[k];
+        o.inertia[k] = p[i].I[k]; o.param[k] = p[i].prm[k];
+      }
+      for (int k = 0; k < 4; ++k) o.quat[k] = p[i].q[k];
+      o.mass = p[i].m;
+      o.volume = p[i].V;
+      o.shape = p[i].shape;
+      o.flags = p[i].flags;
+    }
+  }
+  return HLBM_OK;
+}
+
+int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_device) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  if (mask == 0 || (mask & ~15u)) return fail(HLBM_EINVAL, "mask must select fields 1|2|4|8");
+  if (!out) return fail(HLBM_EINVAL, "out is NULL");
+  int rc = check_status(ctx);
+  if (rc) return rc;
+  if (!ctx->binned) {
+    rc = rebin(ctx);
+    if (rc) return rc;
+  }
+  const long long N = ctx->L.N;
+  const int planes = ((mask & 1u) ? 1 : 0) + ((mask & 2u) ? 3 : 0) + ((mask & 4u) ? 3 : 0) + ((mask & 8u) ? 1 : 0);
+  if (out_on_device) {
+    HIP_TRY(launch_fields(ctx->cfg.precision, ctx->L, ctx->fA, ctx->parts, ctx->tcnt, ctx->tlist, mask, out,
+                          ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return check_status(ctx);
+  }
+  // host output: at most four planes fit the staging area at a time
+  const unsigned bits[4] = {1u, 2u, 4u, 8u};
+  const int width[4] = {1, 3, 3, 1};
+  long long plane = 0;
+  for (int b = 0; b < 4; ++b) {
+    if (!(mask & bits[b])) continue;
+    HIP_TRY(launch_fields(ctx->cfg.precision, ctx->L, ctx->fA, ctx->parts, ctx->tcnt, ctx->tlist, bits[b],
+                          ctx->stage, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(out + plane * N, ctx->stage, sizeof(double) * N * width[b], hipMemcpyDeviceToHost,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    plane += width[b];
+  }
+  (void)planes;
+  return check_status(ctx);
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+"""Thin ctypes binding of ``libhlbm.so`` (the C ABI in ``include/hlbm.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels.
+PyTorch supplies the device workspace and the stream.  Importing this module
+does not load the library; the first use does, and it raises if the built
+library is missing (build it with ``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhlbm.so")
+
+HLBM_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSTABLE", -6: "EUNSUPPORTED"}
+BC_PERIODIC, BC_WALL = 0, 1
+FP64, FP32, FP16S = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
+FIELD_RHO, FIELD_U, FIELD_U_PHYS, FIELD_SOLID = 1, 2, 4, 8
+
+EXPORTED = ["hlbm_workspace_size", "hlbm_init", "hlbm_destroy", "hlbm_set_particles",
+            "hlbm_set_fields", "hlbm_step", "hlbm_get_forces", "hlbm_get_fields",
+            "hlbm_num_particles", "hlbm_last_error"]
+
+
+class hlbm_config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("bc", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
+                ("max_particles", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("eps", ctypes.c_double), ("rho_f", ctypes.c_double),
+                ("gravity", ctypes.c_double * 3), ("fluid_accel", ctypes.c_double * 3),
+                ("stream", ctypes.c_void_p)]
+
+
+# byte layout of struct hlbm_particle
+HLBM_PARTICLE = np.dtype([("pos", "<f8", 3), ("quat", "<f8", 4), ("vel", "<f8", 3),
+                          ("omega", "<f8", 3), ("mass", "<f8"), ("volume", "<f8"),
+                          ("inertia", "<f8", 3), ("param", "<f8", 3), ("shape", "<i4"),
+                          ("flags", "<i4")])
+
+
+class HLBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libhlbm.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        cfgp = ctypes.POINTER(hlbm_config)
+        L.hlbm_workspace_size.argtypes = [cfgp, ctypes.POINTER(ctypes.c_size_t)]
+        L.hlbm_init.argtypes = [cfgp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+        L.hlbm_destroy.argtypes = [vp]
+        L.hlbm_set_particles.argtypes = [vp, i32, vp]
+        L.hlbm_set_fields.argtypes = [vp, vp, vp]
+        L.hlbm_step.argtypes = [vp, i32]
+        L.hlbm_get_forces.argtypes = [vp, vp, vp, vp]
+        L.hlbm_get_fields.argtypes = [vp, ctypes.c_uint32, vp, i32]
+        L.hlbm_num_particles.argtypes = [vp, ctypes.POINTER(i32)]
+        L.hlbm_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name != "hlbm_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != HLBM_OK:
+        raise HLBMError(rc, lib().hlbm_last_error().decode())
+
+
+def make_config(n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps=0.5, rho_f=1.0,
+                gravity=(0.0, 0.0, 0.0), fluid_accel=(0.0, 0.0, 0.0), stream=None):
+    c = hlbm_config()
+    c.nx, c.ny, c.nz = (int(v) for v in n)
+    c.bc = (ctypes.c_int32 * 3)(*[int(b) for b in bc])
+    c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    c.max_particles = int(max_particles)
+    c.tau, c.eps, c.rho_f = float(tau), float(eps), float(rho_f)
+    c.gravity = (ctypes.c_double * 3)(*gravity)
+    c.fluid_accel = (ctypes.c_double * 3)(*fluid_accel)
+    c.stream = stream
+    return c
+
+
+def to_particle_records(particles) -> np.ndarray:
+    """Copy a record array with the fields of ``struct hlbm_particle`` (by
+    name) into the ABI's byte layout."""
+    out = np.zeros(len(particles), dtype=HLBM_PARTICLE)
+    for name in HLBM_PARTICLE.names:
+        out[name] = particles[name]
+    return out
+
+
+class Simulation:
+    """One HLBM context on the current HIP device."""
+
+    def __init__(self, n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps=0.5,
+                 rho_f=1.0, gravity=(0.0, 0.0, 0.0), fluid_accel=(0.0, 0.0, 0.0), device=None,
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.n = tuple(int(v) for v in n)
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        self.cfg = make_config(n, bc, tau, precision, max_particles, eps, rho_f, gravity,
+                               fluid_accel, ctypes.c_void_p(self.stream.cuda_stream))
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().hlbm_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self._ctx = ctypes.c_void_p()
+        _check(lib().hlbm_init(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()),
+                               nbytes.value, ctypes.byref(self._ctx)))
+        self.num_particles = 0
+
+    def close(self):
+        if self._ctx:
+            _check(lib().hlbm_destroy(self._ctx))
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_particles(self, particles):
+        recs = to_particle_records(particles)
+        _check(lib().hlbm_set_particles(self._ctx, len(recs),
+                                        recs.ctypes.data if len(recs) else None))
+        self.num_particles = len(recs)
+
+    def set_fields(self, rho=None, u=None):
+        r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        v = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(3, -1)
+        _check(lib().hlbm_set_fields(self._ctx, None if r is None else r.ctypes.data,
+                                     None if v is None else v.ctypes.data))
+
+    def step(self, nsteps=1):
+        _check(lib().hlbm_step(self._ctx, int(nsteps)))
+
+    def get_forces(self):
+        n = self.num_particles
+        F = np.zeros((max(n, 1), 3))
+        T = np.zeros((max(n, 1), 3))
+        st = np.zeros(max(n, 1), dtype=HLBM_PARTICLE)
+        _check(lib().hlbm_get_forces(self._ctx, F.ctypes.data, T.ctypes.data, st.ctypes.data))
+        return F[:n], T[:n], st[:n]
+
+    def get_fields(self, mask=FIELD_RHO | FIELD_U | FIELD_U_PHYS | FIELD_SOLID, on_device=False):
+        planes = (1 if mask & 1 else 0) + (3 if mask & 2 else 0) + (3 if mask & 4 else 0) + \
+                 (1 if mask & 8 else 0)
+        if on_device:
+            out = self.torch.empty((planes, self.N), dtype=self.torch.float64, device=self.device)
+            _check(lib().hlbm_get_fields(self._ctx, mask, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        out = np.zeros((planes, self.N))
+        _check(lib().hlbm_get_fields(self._ctx, mask, out.ctypes.data, 0))
+        res = {}
+        k = 0
+        if mask & 1:
+            res["rho"] = out[k]; k += 1
+        if mask & 2:
+            res["u"] = out[k:k + 3]; k += 3
+        if mask & 4:
+            res["u_phys"] = out[k:k + 3]; k += 3
+        if mask & 8:
+            res["B"] = out[k]
+        return res

@@ -1,0 +1,185 @@
+"""GPU (HIP, gfx950) HLBM step vs the FP64 CPU oracle on identical seeded
+inputs, through the C ABI.
+
+Tolerances: FP64 storage and arithmetic -- L2-relative velocity <= 1e-12,
+max |rho - rho_ref| <= 1e-14, relative force <= 1e-10 after the workload's
+steps.  The velocity error is taken relative to max(|u_ref|, 1e-4) per cell
+(RMS): the oracle stores f itself, O(1/18), whose FP64 ulp (~7e-18) already
+moves u by ~1e-17, i.e. 1e-11 relative at the |u| ~ 3e-6 of the settling
+sphere, so a purely relative bar would measure the oracle's own round-off;
+FP32 (shifted storage f - w) -- L2-relative velocity <= 1e-5, force <= 1e-4;
+FP16S -- stated error bounds measured against FP64."""
+import numpy as np
+import pytest
+
+from paper_2312_14172_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_14172_amd import hlbm
+    hlbm.lib()
+    return hlbm
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _run_both(H, oracle_mod, n, bc, tau, particles, steps, precision="fp64", gravity=(0, 0, -1e-5),
+              fluid_accel=(0, 0, 0), rho=None, u=None, split=None):
+    sim = H.Simulation(n, bc, tau, precision, max_particles=max(len(particles), 1), gravity=gravity,
+                       fluid_accel=fluid_accel)
+    if rho is not None or u is not None:
+        sim.set_fields(rho, u)
+    sim.set_particles(particles)
+    if split:
+        for s in split:
+            sim.step(s)
+    else:
+        sim.step(steps)
+    F, T, st = sim.get_forces()
+    fl = sim.get_fields()
+    orc = oracle_mod.Oracle(n, bc, tau, gravity=gravity, fluid_accel=fluid_accel)
+    P = orc.to_parts(particles)
+    f = orc.equilibrium(rho, u) if (rho is not None or u is not None) else orc.equilibrium()
+    Fo, To = orc.run(P, f, steps)
+    rho_o, u_o, up_o, B_o = orc.fields(P, f)
+    sim.close()
+    return dict(F=F, T=T, st=st, fl=fl, Fo=Fo, To=To, P=P, rho=rho_o, u=u_o, up=up_o, B=B_o)
+
+
+def _l2rel(a, b, floor=0.0):
+    """||a - b|| / ||b||, with ||b|| floored at `floor` RMS per entry."""
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), floor * np.sqrt(b.size), 1e-300))
+
+
+U_FLOOR = 1e-4
+
+
+def test_single_sphere_fp64_matches_oracle(H, oracle_mod):
+    wl = W.single_sphere()
+    _log("gpu: sphere32 fp64 100 steps")
+    r = _run_both(H, oracle_mod, wl.n, wl.bc, wl.tau, wl.particles, 100)
+    fl = r["fl"]
+    _log(f"  L2rel(u)={_l2rel(fl['u'], r['u']):.3e} floored={_l2rel(fl['u'], r['u'], U_FLOOR):.3e}")
+    assert _l2rel(fl["u"], r["u"], U_FLOOR) <= 1e-12
+    assert np.max(np.abs(fl["rho"] - r["rho"])) <= 1e-14
+    assert _l2rel(fl["u_phys"], r["up"], U_FLOOR) <= 1e-12
+    # B moves with the particle position (parity ~1e-15) at slope <= pi/eps
+    np.testing.assert_allclose(fl["B"], r["B"], rtol=0, atol=1e-12)
+    Fz = r["Fo"][0, 2]
+    assert abs(r["F"][0, 2] - Fz) <= 1e-10 * abs(Fz)
+    assert np.all(np.abs(r["F"][0, :2] - r["Fo"][0, :2]) <= 1e-12 * abs(Fz))
+    assert np.all(np.abs(r["T"][0] - r["To"][0]) <= 1e-12 * abs(Fz))
+    np.testing.assert_allclose(r["st"]["pos"][0], r["P"]["X"][0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["st"]["vel"][0], r["P"]["U"][0], rtol=1e-10, atol=1e-18)
+
+
+@pytest.mark.parametrize("precision,tol_u,tol_F", [("fp32", 1e-5, 1e-4), ("fp16s", 2e-2, 2e-2)])
+def test_single_sphere_reduced_precision(H, oracle_mod, precision, tol_u, tol_F):
+    wl = W.single_sphere()
+    _log(f"gpu: sphere32 {precision} 100 steps")
+    r = _run_both(H, oracle_mod, wl.n, wl.bc, wl.tau, wl.particles, 100, precision=precision)
+    e_u = _l2rel(r["fl"]["u"], r["u"])
+    e_F = abs(r["F"][0, 2] - r["Fo"][0, 2]) / abs(r["Fo"][0, 2])
+    e_rho = float(np.max(np.abs(r["fl"]["rho"] - r["rho"])))
+    _log(f"  {precision}: L2rel(u)={e_u:.3e} relF={e_F:.3e} max|drho|={e_rho:.3e}")
+    assert e_u <= tol_u and e_F <= tol_F
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16s"])
+def test_plain_lbm_from_smooth_fields(H, oracle_mod, precision):
+    """No particles: the step is plain BGK; smooth random initial state on a
+    ragged multi-tile lattice with walls on y and z."""
+    n, bc = (70, 13, 10), (0, 1, 1)
+    rho, u = W.smooth_fields(n, 3, rho_amp=1e-2, u_amp=3e-2)
+    _log(f"gpu: plain lbm {n} {precision}")
+    r = _run_both(H, oracle_mod, n, bc, 0.7, np.zeros(0, dtype=W.PARTICLE_DTYPE), 15,
+                  precision=precision, rho=rho, u=u)
+    tol = {"fp64": 1e-13, "fp32": 1e-5, "fp16s": 5e-3}[precision]
+    e = _l2rel(r["fl"]["u"], r["u"])
+    _log(f"  L2rel(u)={e:.3e}")
+    assert e <= tol
+    assert np.max(np.abs(r["fl"]["rho"] - r["rho"])) <= {"fp64": 1e-14, "fp32": 1e-6, "fp16s": 1e-3}[precision]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_mixed_moving_particles_fp64_ragged_tiles(H, oracle_mod, seed):
+    """Spheres, rounded cubes and spheroids with random orientation, velocity and
+    angular velocity on a lattice that is ragged in every tile dimension, with
+    walls along z; fields and forces after 25 steps (split across calls)."""
+    n, bc = (70, 26, 30), (0, 0, 1)
+    parts = W.random_particles_small(n, 4, seed, r_eq=(2.5, 3.5), bc=bc)
+    rho, u = W.smooth_fields(n, 10 + seed, rho_amp=1e-3, u_amp=1e-2)
+    _log(f"gpu: mixed particles seed {seed}")
+    r = _run_both(H, oracle_mod, n, bc, 0.8, parts, 25, rho=rho, u=u, split=(1, 10, 14))
+    _log(f"  L2rel(u)={_l2rel(r['fl']['u'], r['u']):.3e}")
+    assert _l2rel(r["fl"]["u"], r["u"], U_FLOOR) <= 1e-12
+    assert _l2rel(r["fl"]["u_phys"], r["up"], U_FLOOR) <= 1e-12
+    assert np.max(np.abs(r["fl"]["rho"] - r["rho"])) <= 1e-14
+    np.testing.assert_allclose(r["fl"]["B"], r["B"], rtol=0, atol=1e-13)
+    scale = np.max(np.abs(r["Fo"]))
+    np.testing.assert_allclose(r["F"], r["Fo"], rtol=0, atol=1e-10 * scale)
+    np.testing.assert_allclose(r["T"], r["To"], rtol=0, atol=1e-9 * np.max(np.abs(r["To"])))
+    np.testing.assert_allclose(r["st"]["pos"], r["P"]["X"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["st"]["quat"], r["P"]["q"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["st"]["omega"], r["P"]["W"], rtol=0, atol=1e-13)
+
+
+def test_fields_before_any_step_and_zero_steps(H, oracle_mod):
+    wl = W.single_sphere()
+    sim = H.Simulation(wl.n, wl.bc, wl.tau, "fp64", max_particles=1, gravity=wl.gravity)
+    sim.set_particles(wl.particles)
+    sim.step(0)
+    fl = sim.get_fields()
+    orc = oracle_mod.Oracle(wl.n, wl.bc, wl.tau)
+    rho, u, up, B = orc.fields(orc.to_parts(wl.particles), orc.equilibrium())
+    np.testing.assert_allclose(fl["B"], B, atol=1e-15)
+    assert np.all(fl["rho"] == 1.0) and np.all(fl["u"] == 0.0)
+    F, T, _ = sim.get_forces()
+    assert np.all(F == 0) and np.all(T == 0)
+    sim.close()
+
+
+def test_unstable_state_is_reported(H):
+    """A fluid velocity above the Mach guard, forced from the host, makes the
+    kernels raise the instability flag; the next get_* call reports it."""
+    sim = H.Simulation((16, 8, 8), (0, 0, 0), 0.8, "fp32")
+    u = np.zeros((3, 16 * 8 * 8))
+    u[0] = 0.4
+    sim.set_fields(None, u)
+    sim.step(1)
+    with pytest.raises(H.HLBMError) as e:
+        sim.get_fields()
+    assert e.value.code == -5
+    # after the report the context is usable again
+    sim.set_fields(None, None)
+    sim.step(2)
+    assert np.allclose(sim.get_fields(H.FIELD_RHO)["rho"], 1.0)
+    sim.close()
+
+
+def test_set_particles_validation(H):
+    sim = H.Simulation((32, 32, 32), (0, 0, 1), 0.8, "fp64", max_particles=2)
+    good = np.array([W.make_particle(W.SPHERE, (3.0,), (10, 10, 10))])
+    sim.set_particles(good)
+    bad = good.copy()
+    bad["quat"] = (1, 1, 0, 0)
+    with pytest.raises(H.HLBMError):
+        sim.set_particles(bad)
+    big = np.array([W.make_particle(W.SPHERE, (14.0,), (16, 16, 16))])
+    with pytest.raises(H.HLBMError):
+        sim.set_particles(big)
+    with pytest.raises(H.HLBMError):
+        sim.set_particles(np.concatenate([good, good, good]))
+    out = good.copy()
+    out["pos"] = (10, 10, 40)
+    with pytest.raises(H.HLBMError):
+        sim.set_particles(out)
+    sim.close()
