@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled HLBM step on one MI355X.
+
+One step = momentum exchange -> Newton-Euler -> particle binning -> fused
+collide/stream with the HLBM coupling (all of the hot path), over the whole
+lattice.  MLUPS = cells x steps / (wall time x 1e6), inputs resident in HBM,
+timed with torch.cuda.synchronize() on both sides of exactly K steps.
+
+Prints one JSON line.  Besides the throughput it carries:
+  roofline      -- the collide-and-stream kernel's algorithmic HBM bytes per
+                   launch (2 x 19 populations x bytes each, per cell) divided
+                   by its mean HIP-event duration over the timed region,
+                   against the 8 TB/s HBM peak;
+  force_err_vs_fp64 -- time-averaged per-particle force of this precision
+                   against the FP64 form of the same workload, RMS-relative
+                   over particles (untimed run);
+  cpu_baseline  -- the FP64 CPU oracle on a bounded sample of the workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled HLBM MLUPS + % HBM roofline, FP32/learned vs FP64 at ≤1% force err"
+HBM_PEAK_GBS = 8000.0
+POP_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f32 (f16 storage)"}
+DEFAULT_PRECISION = {"spheres128": "fp32", "sphere32": "fp64", "mixed256": "fp16s"}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2312_14172_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, precision: str):
+    """HBM bytes per collide launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"collide_{workload}_{precision}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def force_error_vs_fp64(H, wl, precision, steps, every):
+    """Time-averaged per-particle force of `precision` vs FP64, RMS-relative."""
+    import numpy as np
+    import torch
+    sums = {}
+    for prec in (precision, "fp64"):
+        sim = H.Simulation(wl.n, wl.bc, wl.tau, prec, max_particles=len(wl.particles),
+                           gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f)
+        sim.set_particles(wl.particles)
+        acc = np.zeros((len(wl.particles), 3))
+        for _ in range(steps // every):
+            sim.step(every)
+            F, _, _ = sim.get_forces()
+            acc += F
+        torch.cuda.synchronize()
+        sims_state = sim.get_forces()[2]
+        sums[prec] = (acc / (steps // every), sims_state)
+        sim.close()
+    a, ref = sums[precision][0], sums["fp64"][0]
+    err = float(np.sqrt(np.mean(np.sum((a - ref) ** 2, axis=1))) /
+                np.sqrt(np.mean(np.sum(ref ** 2, axis=1))))
+    vz = float(np.mean(sums[precision][1]["vel"][:, 2]))
+    vz_ref = float(np.mean(sums["fp64"][1]["vel"][:, 2]))
+    return err, abs(vz - vz_ref) / max(abs(vz_ref), 1e-300)
+
+
+def cpu_baseline(wl, target_s=12.0):
+    """The FP64 oracle as it stands, on a bounded number of steps of the same
+    workload, all host cores (OpenMP)."""
+    from oracle import oracle as orc
+    o = orc.Oracle(wl.n, wl.bc, wl.tau, eps=wl.eps, rho_f=wl.rho_f, gravity=wl.gravity)
+    P = o.to_parts(wl.particles)
+    f = o.equilibrium()
+    t0 = time.perf_counter()
+    o.run(P, f, 1)
+    one = time.perf_counter() - t0
+    steps = max(1, min(200, int(target_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    o.run(P, f, steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(wl.ncells * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": int(o.num_threads()), "kind": "oracle",
+            "sample": f"{wl.name}: {steps} FP64 steps after 1 warm-up step, {dt:.1f} s"}
+
+
+def copy_calibration(nbytes=1 << 31, reps=3):
+    """A plain device copy of known size, for scaling HBM counters."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="spheres128", choices=sorted(DEFAULT_PRECISION))
+    ap.add_argument("--precision", default=None, choices=sorted(POP_BYTES))
+    ap.add_argument("--force-steps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-force-check", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 2 GiB device copy (for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the path is single-GPU by design)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2312_14172_amd import hlbm as H
+    from paper_2312_14172_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    precision = args.precision or DEFAULT_PRECISION[args.workload]
+    wl = W.get(args.workload)
+    print(f"[bench] {wl.name}: {wl.n} cells, {len(wl.particles)} particles, {precision}, "
+          f"phi={wl.solid_fraction:.3f}", file=sys.stderr, flush=True)
+    H.lib()
+    sim = H.Simulation(wl.n, wl.bc, wl.tau, precision, max_particles=len(wl.particles),
+                       gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f)
+    sim.set_particles(wl.particles)
+    sim.step(args.warmup)
+    sim.get_forces()            # synchronises and reports kernel errors
+    torch.cuda.synchronize()
+
+    sim.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    collide_ms, launches = sim.profile_end()
+    sim.get_forces()            # surfaces any kernel-raised error of the timed steps
+    dt = t1 - t0
+    mlups = wl.ncells * args.steps / dt / 1e6
+    print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+
+    alg_bytes = 2 * 19 * POP_BYTES[precision] * wl.ncells
+    per_launch_s = collide_ms / max(launches, 1) / 1e3
+    achieved = alg_bytes / per_launch_s / 1e9
+    traffic = load_traffic(wl.name, precision)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"k_collide<{precision}>",
+                "kernel_ms": round(per_launch_s * 1e3, 5),
+                "bytes_per_launch": alg_bytes}
+    sim.close()
+
+    if args.copy_calibration:
+        copy_calibration()
+
+    extra = {}
+    if not args.no_force_check and precision != "fp64" and len(wl.particles):
+        every = 10
+        err, vz_err = force_error_vs_fp64(H, wl, precision, args.force_steps, every)
+        extra["force_err_vs_fp64"] = float(f"{err:.4g}")
+        extra["settling_velocity_err_vs_fp64"] = float(f"{vz_err:.4g}")
+        extra["force_check"] = f"{args.force_steps} steps from rest, forces sampled every {every}"
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl)
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[precision], "data": "synthetic",
+        "config": {"workload": wl.name, "lattice": list(wl.n), "bc": list(wl.bc),
+                   "particles": int(len(wl.particles)), "solid_fraction": round(wl.solid_fraction, 4),
+                   "tau": wl.tau, "storage": precision, "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,6 +155,14 @@ int hlbm_get_forces(hlbm_ctx *ctx, double *F, double *T, hlbm_particle *state);
  * current integer time and the current particles).  Synchronises the stream. */
 int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_device);
 
+/* Measurement hooks: from hlbm_profile_begin on, every collide-and-stream
+ * launch of hlbm_step is bracketed by two HIP events recorded on the
+ * context's stream.  hlbm_profile_end synchronises the stream, returns the
+ * summed event time in milliseconds and the number of timed launches, and
+ * stops timing. */
+int hlbm_profile_begin(hlbm_ctx *ctx);
+int hlbm_profile_end(hlbm_ctx *ctx, double *collide_ms, int64_t *launches);
+
 /* Number of particles currently held. */
 int hlbm_num_particles(const hlbm_ctx *ctx, int32_t *n);
 

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include <string>
@@ -36,10 +37,13 @@ int fail(int code, const char *fmt, ...) {
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// z-layers a particle's momentum-exchange box can span (circumradius <= 27)
+constexpr int LMAX_CAP = 56;
+
 size_t pop_bytes(int precision) { return precision == HLBM_FP64 ? 8 : (precision == HLBM_FP32 ? 4 : 2); }
 
 struct Layout {
-  size_t fA, fB, parts, stage_parts, tcnt, tlist, partial, status, stage, total;
+  size_t fA, fB, parts, stage_parts, tcnt[2], tlist[2], partial, status, stage, total;
 };
 
 int validate(const hlbm_config *c) {
@@ -86,9 +90,11 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
   y.fB = off; off += pop;
   y.parts = off; off += align_up(np * sizeof(DevParticle));
   y.stage_parts = off; off += align_up(np * sizeof(hlbm_particle));
-  y.tcnt = off; off += align_up((size_t)L.ntiles * sizeof(int));
-  y.tlist = off; off += align_up((size_t)L.ntiles * MAXC * sizeof(int));
-  y.partial = off; off += align_up((size_t)L.ntiles * MAXC * 6 * sizeof(double));
+  for (int b = 0; b < 2; ++b) {
+    y.tcnt[b] = off; off += align_up((size_t)L.ntiles * sizeof(int));
+    y.tlist[b] = off; off += align_up((size_t)L.ntiles * MAXC * sizeof(int));
+  }
+  y.partial = off; off += align_up(np * LMAX_CAP * 6 * sizeof(double));
   y.status = off; off += 256;
   y.stage = off; off += align_up((size_t)4 * L.N * sizeof(double));
   y.total = off + 256;  // slack for aligning the caller's base pointer
@@ -106,12 +112,17 @@ struct hlbm_ctx {
   void *fA, *fB;
   DevParticle *parts;
   hlbm_particle *stage_parts;
-  int *tcnt, *tlist, *status;
+  int *tcnt[2], *tlist[2], *status;
+  int cur;            // tile-list buffer describing the current particles
   double *partial, *stage;
+  int lmax;           // z-layers of the largest momentum-exchange box
   int n;
+  int bin_cap;        // tiles a particle's coupling box can touch (bin grid width)
   bool binned;        // tile lists describe the current particles
-  bool forces_ready;  // partial records hold the momentum exchange of the current state
   long long steps_done;
+  bool profiling;
+  std::vector<hipEvent_t> events;  // start/stop pairs around collide launches
+  size_t events_used;
 };
 
 namespace {
@@ -132,8 +143,10 @@ int check_status(hlbm_ctx *c) {
 }
 
 int rebin(hlbm_ctx *c) {
-  HIP_TRY(launch_fill_int(c->tcnt, 0, c->L.ntiles, c->stream));
-  HIP_TRY(launch_bin(c->L, c->parts, c->n, c->tcnt, c->tlist, c->status, c->stream));
+  HIP_TRY(launch_fill_int(c->tcnt[0], 0, c->L.ntiles, c->stream));
+  HIP_TRY(launch_fill_int(c->tcnt[1], 0, c->L.ntiles, c->stream));
+  HIP_TRY(launch_bin(c->L, c->parts, c->n, c->bin_cap, c->tcnt[c->cur], c->tlist[c->cur], c->status,
+                     c->stream));
   c->binned = true;
   return HLBM_OK;
 }
@@ -178,18 +191,25 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   c->fB = c->base + lay.fB;
   c->parts = (DevParticle *)(c->base + lay.parts);
   c->stage_parts = (hlbm_particle *)(c->base + lay.stage_parts);
-  c->tcnt = (int *)(c->base + lay.tcnt);
-  c->tlist = (int *)(c->base + lay.tlist);
+  for (int b = 0; b < 2; ++b) {
+    c->tcnt[b] = (int *)(c->base + lay.tcnt[b]);
+    c->tlist[b] = (int *)(c->base + lay.tlist[b]);
+  }
+  c->cur = 0;
   c->partial = (double *)(c->base + lay.partial);
+  c->lmax = 1;
   c->status = (int *)(c->base + lay.status);
   c->stage = (double *)(c->base + lay.stage);
   c->n = 0;
   c->binned = false;
-  c->forces_ready = false;
+  c->bin_cap = 1;
   c->steps_done = 0;
+  c->profiling = false;
+  c->events_used = 0;
   // rest state: every deviation f_i - w_i is zero
   hipError_t e = hipMemsetAsync(c->fA, 0, (size_t)19 * L.N * pop_bytes(cfg->precision), c->stream);
-  if (e == hipSuccess) e = launch_fill_int(c->tcnt, 0, L.ntiles, c->stream);
+  if (e == hipSuccess) e = launch_fill_int(c->tcnt[0], 0, L.ntiles, c->stream);
+  if (e == hipSuccess) e = launch_fill_int(c->tcnt[1], 0, L.ntiles, c->stream);
   if (e == hipSuccess) e = launch_fill_int(c->status, 0, 1, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -204,7 +224,32 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
 int hlbm_destroy(hlbm_ctx *ctx) {
   if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
   (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   delete ctx;
+  return HLBM_OK;
+}
+
+int hlbm_profile_begin(hlbm_ctx *ctx) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  ctx->profiling = true;
+  ctx->events_used = 0;
+  return HLBM_OK;
+}
+
+int hlbm_profile_end(hlbm_ctx *ctx, double *collide_ms, int64_t *launches) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  if (!ctx->profiling) return fail(HLBM_ESTATE, "profiling was not started");
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  double total = 0.0;
+  for (size_t k = 0; k + 1 < ctx->events_used; k += 2) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->events[k], ctx->events[k + 1]));
+    total += ms;
+  }
+  if (collide_ms) *collide_ms = total;
+  if (launches) *launches = (int64_t)(ctx->events_used / 2);
+  ctx->profiling = false;
+  ctx->events_used = 0;
   return HLBM_OK;
 }
 
@@ -220,6 +265,7 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
     return fail(HLBM_EINVAL, "n = %d outside [0, max_particles = %d]", n, ctx->cfg.max_particles);
   if (n > 0 && !host) return fail(HLBM_EINVAL, "particles is NULL");
   const int nn[3] = {ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.nz};
+  int cap = 1, lmax = 1;
   for (int i = 0; i < n; ++i) {
     const hlbm_particle &p = host[i];
     const double *vals[] = {p.pos, p.quat, p.vel, p.omega, p.inertia, p.param};
@@ -254,16 +300,26 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
       if (ctx->cfg.bc[k] == HLBM_BC_WALL && !(p.pos[k] >= 0 && p.pos[k] <= nn[k]))
         return fail(HLBM_EINVAL, "particle %d: centre outside the walls", i);
     }
-    // a reach box spans at most 2 reach + 1 cells: 16 tiles of 4 cells per axis
-    if (reach > 28.0) return fail(HLBM_EUNSUPPORTED, "particle %d: circumradius above 25 cells", i);
+    // the coupling box spans at most floor(2 (rc + eps/2)) + 1 cells per axis;
+    // the binning handles up to MAX_AXIS_TILES tiles of 4 cells per axis
+    const int cells = (int)floor(2.0 * (rc + 0.5 * ctx->cfg.eps)) + 2;
+    if (cells / TY + 2 > MAX_AXIS_TILES)
+      return fail(HLBM_EUNSUPPORTED, "particle %d: circumradius too large for the tile binning", i);
+    const int tiles_x = std::min(ctx->L.ntx, cells / TX + 2);
+    const int tiles_y = std::min(ctx->L.nty, cells / TY + 2);
+    const int tiles_z = std::min(ctx->L.ntz, cells / TZ + 2);
+    cap = std::max(cap, tiles_x * tiles_y * tiles_z);
+    lmax = std::max(lmax, (int)floor(2.0 * rc) + 2);
   }
+  if (lmax > LMAX_CAP) return fail(HLBM_EUNSUPPORTED, "circumradius too large");
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   if (n > 0) {
     HIP_TRY(hipMemcpyAsync(ctx->stage_parts, host, sizeof(hlbm_particle) * n, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(launch_prepare(ctx->L, ctx->stage_parts, ctx->parts, n, ctx->stream));
   }
   ctx->n = n;
-  ctx->forces_ready = false;
+  ctx->bin_cap = cap;
+  ctx->lmax = lmax;
   int rc = rebin(ctx);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -285,7 +341,6 @@ int hlbm_set_fields(hlbm_ctx *ctx, const double *rho, const double *u) {
   }
   HIP_TRY(launch_set_fields(ctx->cfg.precision, ctx->L, ctx->fA, drho, du, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
-  ctx->forces_ready = false;
   return HLBM_OK;
 }
 
@@ -295,25 +350,34 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
   const int prec = ctx->cfg.precision;
   hipStream_t s = ctx->stream;
   for (int it = 0; it < nsteps; ++it) {
+    const int nxt = 1 - ctx->cur;
     if (ctx->n > 0) {
-      if (!ctx->binned) {
-        int rc = rebin(ctx);
-        if (rc) return rc;
-      }
-      if (!ctx->forces_ready) {
-        HIP_TRY(launch_mea_pull(prec, ctx->L, ctx->fA, ctx->parts, ctx->tcnt, ctx->tlist, ctx->partial, s));
-        ctx->forces_ready = true;
-      }
-      HIP_TRY(launch_eom(ctx->L, ctx->parts, ctx->n, ctx->tcnt, ctx->tlist, ctx->partial, ctx->status, s));
-      int rc = rebin(ctx);
-      if (rc) return rc;
+      // momentum exchange on the state of time t, then Newton-Euler -> t+1 and
+      // binning of the updated particles into the other tile-list buffer
+      HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->n, ctx->lmax, ctx->partial, s));
+      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, ctx->partial, ctx->tcnt[nxt],
+                             ctx->tlist[nxt], ctx->status, s));
     }
-    HIP_TRY(launch_collide(prec, ctx->L, ctx->fA, ctx->fB, ctx->parts, ctx->tcnt, ctx->tlist, ctx->partial,
+    const int use = ctx->n > 0 ? nxt : ctx->cur;
+    int *clear = ctx->n > 0 ? ctx->tcnt[ctx->cur] : nullptr;
+    if (ctx->profiling) {
+      while (ctx->events.size() < ctx->events_used + 2) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        ctx->events.push_back(e);
+      }
+      HIP_TRY(hipEventRecord(ctx->events[ctx->events_used], s));
+    }
+    HIP_TRY(launch_collide(prec, ctx->L, ctx->fA, ctx->fB, ctx->parts, ctx->tcnt[use], ctx->tlist[use], clear,
                            ctx->status, s));
+    ctx->cur = use;
+    if (ctx->profiling) {
+      HIP_TRY(hipEventRecord(ctx->events[ctx->events_used + 1], s));
+      ctx->events_used += 2;
+    }
     void *t = ctx->fA;
     ctx->fA = ctx->fB;
     ctx->fB = t;
-    ctx->forces_ready = ctx->n > 0;
     ctx->steps_done++;
   }
   return HLBM_OK;
@@ -360,8 +424,8 @@ int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_de
   const long long N = ctx->L.N;
   const int planes = ((mask & 1u) ? 1 : 0) + ((mask & 2u) ? 3 : 0) + ((mask & 4u) ? 3 : 0) + ((mask & 8u) ? 1 : 0);
   if (out_on_device) {
-    HIP_TRY(launch_fields(ctx->cfg.precision, ctx->L, ctx->fA, ctx->parts, ctx->tcnt, ctx->tlist, mask, out,
-                          ctx->stream));
+    HIP_TRY(launch_fields(ctx->cfg.precision, ctx->L, ctx->fA, ctx->parts, ctx->tcnt[ctx->cur],
+                          ctx->tlist[ctx->cur], mask, out, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return check_status(ctx);
   }
@@ -371,8 +435,8 @@ int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_de
   long long plane = 0;
   for (int b = 0; b < 4; ++b) {
     if (!(mask & bits[b])) continue;
-    HIP_TRY(launch_fields(ctx->cfg.precision, ctx->L, ctx->fA, ctx->parts, ctx->tcnt, ctx->tlist, bits[b],
-                          ctx->stage, ctx->stream));
+    HIP_TRY(launch_fields(ctx->cfg.precision, ctx->L, ctx->fA, ctx->parts, ctx->tcnt[ctx->cur],
+                          ctx->tlist[ctx->cur], bits[b], ctx->stage, ctx->stream));
     HIP_TRY(hipMemcpyAsync(out + plane * N, ctx->stage, sizeof(double) * N * width[b], hipMemcpyDeviceToHost,
                            ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -25,7 +25,8 @@ __host__ __device__ constexpr double wgt(int i) {
 constexpr int TX = 64;
 constexpr int TY = 4;
 constexpr int TZ = 4;
-constexpr int MAXC = 48;  // particles a tile can list
+constexpr int MAXC = 48;        // particles a tile can list
+constexpr int MAX_AXIS_TILES = 16;
 
 // Status bits raised by kernels.
 constexpr int ST_UNSTABLE = 1;
@@ -52,29 +53,20 @@ struct DevParticle {
   double m, V, I[3], prm[3];
   double R[9];     // body -> world rotation, row-major
   double rc;       // circumradius
-  double reach;    // rc + max(eps/2, sqrt 2): cells farther away never couple
   double Fh[3];    // hydrodynamic force of the last momentum exchange
   double Th[3];    // hydrodynamic torque of the last momentum exchange
   int shape, flags;
-  int lo[3], hi[3];  // cell range of the reach box (unwrapped coordinates)
-};
-
-// Candidate particle of a tile, staged in LDS.
-struct Cand {
-  double X[3], U[3], W[3];
-  double R[9];
-  double p0, p1;
-  double reach2;
-  int shape;
-  int slot;
+  int lo[3], hi[3];  // cells that can have B > 0 (centre within rc + eps/2), unwrapped
 };
 
 // ---------------------------------------------------------------------------
 // Population storage.  All formats hold the deviation g_i = f_i - w_i.
+// G is the precision of the particle geometry in the lattice kernels.
 // ---------------------------------------------------------------------------
 struct StoreF64 {
   using S = double;
   using T = double;
+  using G = double;
   static constexpr int kind = 0;
   __device__ static inline T dec(S v, int) { return v; }
   __device__ static inline S enc(T g, int) { return g; }
@@ -82,6 +74,7 @@ struct StoreF64 {
 struct StoreF32 {
   using S = float;
   using T = float;
+  using G = float;
   static constexpr int kind = 1;
   __device__ static inline T dec(S v, int) { return v; }
   __device__ static inline S enc(T g, int) { return g; }
@@ -91,6 +84,7 @@ struct StoreF32 {
 struct StoreF16S {
   using S = _Float16;
   using T = float;
+  using G = float;
   static constexpr int kind = 2;
   __device__ static inline T dec(S v, int i) {
     return (float)v * (i == 0 ? (1.0f / 768.0f) : (i <= 6 ? (1.0f / 4608.0f) : (1.0f / 9216.0f)));
@@ -101,70 +95,87 @@ struct StoreF16S {
 };
 
 // ---------------------------------------------------------------------------
-// Geometry (FP64).  Signed distances are negative inside (Sec. 3.2).
+// Geometry.  Signed distances are negative inside (Sec. 3.2).
 // ---------------------------------------------------------------------------
-__device__ inline double min_image(double d, int n, int periodic) {
-  if (periodic) {
-    double h = 0.5 * n;
-    if (d > h) d -= n;
-    else if (d < -h) d += n;
-  }
-  return d;
-}
+__device__ inline double dsqrt(double v) { return sqrt(v); }
+__device__ inline float dsqrt(float v) { return sqrtf(v); }
+__device__ inline double dcos(double v) { return cos(v); }
+__device__ inline float dcos(float v) { return cosf(v); }
+__device__ inline double dabs(double v) { return fabs(v); }
+__device__ inline float dabs(float v) { return fabsf(v); }
+__device__ inline double dmax(double a, double b) { return fmax(a, b); }
+__device__ inline float dmax(float a, float b) { return fmaxf(a, b); }
+__device__ inline double dmin(double a, double b) { return fmin(a, b); }
+__device__ inline float dmin(float a, float b) { return fminf(a, b); }
 
 // Distance from (y0, y1) >= 0 to the ellipse (u/e0)^2 + (v/e1)^2 = 1, e0 >= e1.
 // The nearest point is x_k = e_k^2 y_k / (t + e_k^2) where t is the root of
 // G(t) = sum_k (e_k y_k / (t + e_k^2))^2 - 1.  G is convex and decreasing for
 // t > -e1^2, so Newton's method started at t0 = e1 y1 - e1^2 (G >= 0 there)
 // increases monotonically to the root.
-__device__ inline double ellipse_distance(double e0, double e1, double y0, double y1) {
-  const double e0s = e0 * e0, e1s = e1 * e1;
-  if (y1 > 0.0) {
-    if (y0 > 0.0) {
-      const double a = e0 * y0, b = e1 * y1;
-      double t = b - e1s;
+template <typename G>
+__device__ inline G ellipse_distance(G e0, G e1, G y0, G y1) {
+  const G e0s = e0 * e0, e1s = e1 * e1;
+  if (y1 > G(0)) {
+    if (y0 > G(0)) {
+      const G a = e0 * y0, b = e1 * y1;
+      G t = b - e1s;
       for (int it = 0; it < 100; ++it) {
-        const double p0 = t + e0s, p1 = t + e1s;
-        const double r0 = a / p0, r1 = b / p1;
-        const double G = r0 * r0 + r1 * r1 - 1.0;
-        const double dG = -2.0 * (r0 * r0 / p0 + r1 * r1 / p1);
-        const double tn = t - G / dG;
+        const G p0 = t + e0s, p1 = t + e1s;
+        const G r0 = a / p0, r1 = b / p1;
+        const G gv = r0 * r0 + r1 * r1 - G(1);
+        const G dg = G(-2) * (r0 * r0 / p0 + r1 * r1 / p1);
+        const G tn = t - gv / dg;
         if (!(tn > t)) break;
         t = tn;
       }
-      const double x0 = e0s * y0 / (t + e0s), x1 = e1s * y1 / (t + e1s);
-      return sqrt((x0 - y0) * (x0 - y0) + (x1 - y1) * (x1 - y1));
+      const G x0 = e0s * y0 / (t + e0s), x1 = e1s * y1 / (t + e1s);
+      return dsqrt((x0 - y0) * (x0 - y0) + (x1 - y1) * (x1 - y1));
     }
-    return fabs(y1 - e1);
+    return dabs(y1 - e1);
   }
-  const double den = e0s - e1s;
+  const G den = e0s - e1s;
   if (e0 * y0 < den) {
-    const double x0 = e0s * y0 / den;
-    const double s = x0 / e0;
-    const double x1 = e1 * sqrt(fmax(0.0, 1.0 - s * s));
-    return sqrt((x0 - y0) * (x0 - y0) + x1 * x1);
+    const G x0 = e0s * y0 / den;
+    const G s = x0 / e0;
+    const G x1 = e1 * dsqrt(dmax(G(0), G(1) - s * s));
+    return dsqrt((x0 - y0) * (x0 - y0) + x1 * x1);
   }
-  return fabs(y0 - e0);
+  return dabs(y0 - e0);
 }
 
-// Body-frame signed distance.  Only called where |d| may be below eps/2 or the
-// sign is needed; far-field cells are classified before calling.
-__device__ inline double sdf_body(int shape, double p0, double p1, double b0, double b1, double b2) {
-  if (shape == 0) return sqrt(b0 * b0 + b1 * b1 + b2 * b2) - p0;
+// Body-frame signed distance of a rounded cube or spheroid (shape 1, 2).
+template <typename G>
+__device__ inline G sdf_body(int shape, G p0, G p1, G b0, G b1, G b2) {
+  if (shape == 0) return dsqrt(b0 * b0 + b1 * b1 + b2 * b2) - p0;
   if (shape == 1) {
-    const double core = p0 - p1;
-    const double q0 = fabs(b0) - core, q1 = fabs(b1) - core, q2 = fabs(b2) - core;
-    const double o0 = fmax(q0, 0.0), o1 = fmax(q1, 0.0), o2 = fmax(q2, 0.0);
-    return sqrt(o0 * o0 + o1 * o1 + o2 * o2) + fmin(fmax(q0, fmax(q1, q2)), 0.0) - p1;
+    const G core = p0 - p1;
+    const G q0 = dabs(b0) - core, q1 = dabs(b1) - core, q2 = dabs(b2) - core;
+    const G o0 = dmax(q0, G(0)), o1 = dmax(q1, G(0)), o2 = dmax(q2, G(0));
+    return dsqrt(o0 * o0 + o1 * o1 + o2 * o2) + dmin(dmax(q0, dmax(q1, q2)), G(0)) - p1;
   }
   // spheroid: symmetry axis body x (semi-axis p0), equal semi-axes p1
-  const double y0 = fabs(b0), y1 = sqrt(b1 * b1 + b2 * b2);
-  const double d = (p0 >= p1) ? ellipse_distance(p0, p1, y0, y1) : ellipse_distance(p1, p0, y1, y0);
-  const double k = (b0 * b0) / (p0 * p0) + (b1 * b1 + b2 * b2) / (p1 * p1);
-  return k <= 1.0 ? -d : d;
+  const G y0 = dabs(b0), y1 = dsqrt(b1 * b1 + b2 * b2);
+  const G d = (p0 >= p1) ? ellipse_distance<G>(p0, p1, y0, y1) : ellipse_distance<G>(p1, p0, y1, y0);
+  const G k = (b0 * b0) / (p0 * p0) + (b1 * b1 + b2 * b2) / (p1 * p1);
+  return k <= G(1) ? -d : d;
 }
 
-// Inside test d_s <= 0 from the shape's implicit form.
+// Signed distance for the indicator, with a cheap classification of cells that
+// are certainly farther than eps/2 from the surface: returns +-1e30 there.
+template <typename G>
+__device__ inline G sdf_for_indicator(int shape, G p0, G p1, G b0, G b1, G b2, G half_eps) {
+  if (shape == 2) {
+    // s^2 = implicit value; |d| >= |s - 1| * min(p0, p1) (the scaled spheroids
+    // s E and E are at least that far apart), so only a thin shell iterates.
+    const G k = (b0 * b0) / (p0 * p0) + (b1 * b1 + b2 * b2) / (p1 * p1);
+    const G s = dsqrt(k);
+    if (dabs(s - G(1)) * dmin(p0, p1) >= half_eps) return k <= G(1) ? G(-1e30) : G(1e30);
+  }
+  return sdf_body<G>(shape, p0, p1, b0, b1, b2);
+}
+
+// Inside test d_s <= 0 from the shape's implicit form (FP64).
 __device__ inline bool inside_body(int shape, double p0, double p1, double b0, double b1, double b2) {
   if (shape == 0) return b0 * b0 + b1 * b1 + b2 * b2 <= p0 * p0;
   if (shape == 1) {
@@ -177,26 +188,13 @@ __device__ inline bool inside_body(int shape, double p0, double p1, double b0, d
   return (b0 * b0) / (p0 * p0) + (b1 * b1 + b2 * b2) / (p1 * p1) <= 1.0;
 }
 
-// Signed distance for the indicator, with a cheap classification of cells that
-// are certainly farther than eps/2 from the surface: returns +-BIG there.
-__device__ inline double sdf_for_indicator(int shape, double p0, double p1, double b0, double b1,
-                                           double b2, double half_eps) {
-  if (shape == 2) {
-    // s^2 = implicit value; |d| >= |s - 1| * min(p0, p1) (the scaled spheroids
-    // s E and E are at least that far apart), so only a thin shell iterates.
-    const double k = (b0 * b0) / (p0 * p0) + (b1 * b1 + b2 * b2) / (p1 * p1);
-    const double s = sqrt(k);
-    if (fabs(s - 1.0) * fmin(p0, p1) >= half_eps) return k <= 1.0 ? -1e30 : 1e30;
-  }
-  return sdf_body(shape, p0, p1, b0, b1, b2);
-}
-
 // Trigonometric indicator B(d) (Sec. 3.2 level-set equation), read as
 // cos^2((pi/2)(d/eps + 1/2)) inside the band |d| < eps/2.
-__device__ inline double indicator(double d, double eps) {
-  if (d <= -0.5 * eps) return 1.0;
-  if (d >= 0.5 * eps) return 0.0;
-  const double c = cos(1.5707963267948966 * (d / eps + 0.5));
+template <typename G>
+__device__ inline G indicator(G d, G eps) {
+  if (d <= G(-0.5) * eps) return G(1);
+  if (d >= G(0.5) * eps) return G(0);
+  const G c = dcos(G(1.5707963267948966) * (d / eps + G(0.5)));
   return c * c;
 }
 

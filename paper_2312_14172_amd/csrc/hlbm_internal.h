@@ -10,14 +10,14 @@ namespace hlbm {
 
 hipError_t launch_prepare(const Lattice &L, const hlbm_particle *in, DevParticle *out, int n, hipStream_t s);
 hipError_t launch_fill_int(int *p, int v, int n, hipStream_t s);
-hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int *tcnt, int *tlist, int *status,
-                      hipStream_t s);
-hipError_t launch_eom(const Lattice &L, DevParticle *parts, int n, const int *tcnt, const int *tlist,
-                      const double *partial, int *status, hipStream_t s);
+hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int cap, int *tcnt, int *tlist,
+                      int *status, hipStream_t s);
+hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevParticle *parts, int n, int lmax,
+                      double *partial, hipStream_t s);
+hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, const double *partial,
+                          int *tcnt, int *tlist, int *status, hipStream_t s);
 hipError_t launch_collide(int prec, const Lattice &L, const void *A, void *B, const DevParticle *parts,
-                          const int *tcnt, const int *tlist, double *partial, int *status, hipStream_t s);
-hipError_t launch_mea_pull(int prec, const Lattice &L, const void *A, const DevParticle *parts,
-                           const int *tcnt, const int *tlist, double *partial, hipStream_t s);
+                          const int *tcnt, const int *tlist, int *tcnt_clear, int *status, hipStream_t s);
 hipError_t launch_set_fields(int prec, const Lattice &L, void *A, const double *rho, const double *u,
                              hipStream_t s);
 hipError_t launch_fields(int prec, const Lattice &L, const void *A, const DevParticle *parts,

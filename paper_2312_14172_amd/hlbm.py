@@ -24,7 +24,7 @@ FIELD_RHO, FIELD_U, FIELD_U_PHYS, FIELD_SOLID = 1, 2, 4, 8
 
 EXPORTED = ["hlbm_workspace_size", "hlbm_init", "hlbm_destroy", "hlbm_set_particles",
             "hlbm_set_fields", "hlbm_step", "hlbm_get_forces", "hlbm_get_fields",
-            "hlbm_num_particles", "hlbm_last_error"]
+            "hlbm_num_particles", "hlbm_profile_begin", "hlbm_profile_end", "hlbm_last_error"]
 
 
 class hlbm_config(ctypes.Structure):
@@ -71,6 +71,9 @@ def lib():
         L.hlbm_get_forces.argtypes = [vp, vp, vp, vp]
         L.hlbm_get_fields.argtypes = [vp, ctypes.c_uint32, vp, i32]
         L.hlbm_num_particles.argtypes = [vp, ctypes.POINTER(i32)]
+        L.hlbm_profile_begin.argtypes = [vp]
+        L.hlbm_profile_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]
         L.hlbm_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name != "hlbm_last_error":
@@ -154,6 +157,16 @@ class Simulation:
 
     def step(self, nsteps=1):
         _check(lib().hlbm_step(self._ctx, int(nsteps)))
+
+    def profile_begin(self):
+        _check(lib().hlbm_profile_begin(self._ctx))
+
+    def profile_end(self):
+        """Summed HIP-event time (ms) and count of the collide launches."""
+        ms = ctypes.c_double(0)
+        cnt = ctypes.c_int64(0)
+        _check(lib().hlbm_profile_end(self._ctx, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
 
     def get_forces(self):
         n = self.num_particles

@@ -142,36 +142,54 @@ def shoemake_quaternion(rng: np.random.Generator):
 # ---------------------------------------------------------------------------
 # Random sequential addition on circumspheres
 # ---------------------------------------------------------------------------
-def rsa_positions(rng, radii, n, bc, gap=1.0, wall_margin=1.0, batch=512, max_batches=20000):
+def rsa_positions(rng, radii, n, bc, gap=1.0, wall_margin=1.0, batch=64, max_attempts=5_000_000):
     """Place spheres of the given radii (in the given order) uniformly at
     random without overlap: centre distance >= r_i + r_j + gap, minimum image
-    on periodic axes, and at least r + wall_margin from a wall."""
+    on periodic axes, and at least r + wall_margin from a wall.  Candidates are
+    checked against the already placed spheres of the neighbouring buckets of
+    a uniform grid."""
     n = np.asarray(n, dtype=np.float64)
     bc = np.asarray(bc)
+    radii = np.asarray(radii, dtype=np.float64)
+    rmax = float(radii.max()) if len(radii) else 1.0
+    h = 2 * rmax + gap
+    nb = np.maximum(1, np.floor(n / h)).astype(int)
+    hs = n / nb
+    buckets = {}
     pos = np.zeros((len(radii), 3))
-    placed = 0
-    batches = 0
-    while placed < len(radii):
-        r = radii[placed]
+    per = bc == 0
+    attempts = 0
+    for i, r in enumerate(radii):
         lo = np.where(bc == 1, r + wall_margin, 0.0)
         hi = np.where(bc == 1, n - r - wall_margin, n)
-        cand = lo + (hi - lo) * rng.random((batch, 3))
-        if placed:
-            d = cand[:, None, :] - pos[None, :placed, :]
-            per = bc == 0
-            d[..., per] -= n[per] * np.round(d[..., per] / n[per])
-            dist = np.sqrt(np.sum(d * d, axis=-1))
-            ok = np.all(dist >= radii[None, :placed] + r + gap, axis=1)
-        else:
-            ok = np.ones(batch, dtype=bool)
-        idx = np.flatnonzero(ok)
-        if idx.size:
-            pos[placed] = cand[idx[0]]
-            placed += 1
-        else:
-            batches += 1
-            if batches > max_batches:
-                raise RuntimeError(f"RSA stalled after placing {placed} of {len(radii)}")
+        placed = False
+        while not placed:
+            cand = lo + (hi - lo) * rng.random((batch, 3))
+            for c in cand:
+                attempts += 1
+                if attempts > max_attempts:
+                    raise RuntimeError(f"RSA stalled after placing {i} of {len(radii)}")
+                cell = np.minimum((c // hs).astype(int), nb - 1)
+                near = []
+                for dz in (-1, 0, 1):
+                    for dy in (-1, 0, 1):
+                        for dx in (-1, 0, 1):
+                            k = cell + (dx, dy, dz)
+                            if np.any((k < 0) | (k >= nb)):
+                                if np.any(((k < 0) | (k >= nb)) & ~per):
+                                    continue
+                                k = k % nb
+                            near.extend(buckets.get(tuple(k), ()))
+                if near:
+                    idx = np.array(near)
+                    d = pos[idx] - c
+                    d[:, per] -= n[per] * np.round(d[:, per] / n[per])
+                    if np.any(np.sqrt(np.sum(d * d, axis=1)) < radii[idx] + r + gap):
+                        continue
+                pos[i] = c
+                buckets.setdefault(tuple(cell), []).append(i)
+                placed = True
+                break
     return pos
 
 

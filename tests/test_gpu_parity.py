@@ -78,7 +78,9 @@ def test_single_sphere_fp64_matches_oracle(H, oracle_mod):
     assert np.all(np.abs(r["F"][0, :2] - r["Fo"][0, :2]) <= 1e-12 * abs(Fz))
     assert np.all(np.abs(r["T"][0] - r["To"][0]) <= 1e-12 * abs(Fz))
     np.testing.assert_allclose(r["st"]["pos"][0], r["P"]["X"][0], rtol=0, atol=1e-12)
-    np.testing.assert_allclose(r["st"]["vel"][0], r["P"]["U"][0], rtol=1e-10, atol=1e-18)
+    # x, y velocity components are round-off (the setup is mirror-symmetric)
+    np.testing.assert_allclose(r["st"]["vel"][0], r["P"]["U"][0], rtol=0,
+                               atol=1e-10 * np.max(np.abs(r["P"]["U"][0])))
 
 
 @pytest.mark.parametrize("precision,tol_u,tol_F", [("fp32", 1e-5, 1e-4), ("fp16s", 2e-2, 2e-2)])
