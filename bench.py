@@ -48,14 +48,18 @@ def kernel_source_hash() -> str:
 def load_traffic(workload: str, precision: str):
     """HBM bytes per collide launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"collide_{workload}_{precision}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"collide_{workload}_{precision}_traffic.txt")
     if not os.path.exists(path):
         return None
+    rec = {}
     with open(path) as fh:
-        rec = json.load(fh)
+        for line in fh:
+            if "=" in line and line.startswith("    "):
+                k, v = line.split("=", 1)
+                rec[k.strip()] = v.strip()
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return int(rec["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in rec else None
 
 
 def force_error_vs_fp64(H, wl, precision, steps, every):
