@@ -333,3 +333,28 @@ def get(name: str, **kw) -> Workload:
     if name == "mixed256_learned":
         return mixed_shapes(learned=True, **kw)
     raise KeyError(name)
+
+
+# ---------------------------------------------------------------------------
+# Signed-distance surrogate network: initial parameters and sample points
+# ---------------------------------------------------------------------------
+MLP_HIDDEN = 64
+MLP_NPARAM = 64 * 3 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def mlp_init_params(seed):
+    """Initial network parameters (uniform, He-style limits sqrt(6 / fan_in),
+    zero biases) as one flat float32 vector in the order W1 (64x3), b1,
+    W2 (64x64), b2, W3 (64x64), b3, W4 (64), b4."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-math.sqrt(6 / 3), math.sqrt(6 / 3), 64 * 3), np.zeros(64),
+             rng.uniform(-math.sqrt(6 / 64), math.sqrt(6 / 64), 64 * 64), np.zeros(64),
+             rng.uniform(-math.sqrt(6 / 64), math.sqrt(6 / 64), 64 * 64), np.zeros(64),
+             rng.uniform(-math.sqrt(6 / 64), math.sqrt(6 / 64), 64), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_points(seed, n, half=1.1):
+    """n points uniform in the cube [-half, half]^3 (normalised body frame)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-half, half, (n, 3))
