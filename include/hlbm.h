@@ -89,6 +89,11 @@ typedef struct hlbm_config {
     double gravity[3];    /* gravity vector g (e.g. {0, 0, -1e-5}) */
     double fluid_accel[3];/* body acceleration of the fluid outside the solid */
     void *stream;         /* hipStream_t, NULL = default stream */
+    int32_t learned;      /* 1: reserve memory for learned indicators (networks,
+                             training samples, per-particle distance tables) */
+    int32_t learned_samples; /* training + held-out sample capacity (0 = 1.2e6) */
+    double learned_max_circumradius; /* largest circumradius of a particle that
+                             may use a learned indicator (sizes the tables) */
 } hlbm_config;
 
 typedef struct hlbm_particle {
@@ -162,6 +167,79 @@ int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_de
  * stops timing. */
 int hlbm_profile_begin(hlbm_ctx *ctx);
 int hlbm_profile_end(hlbm_ctx *ctx, double *collide_ms, int64_t *launches);
+
+/* ------------------------------------------------------------------------
+ * Learned indicator (not part of the paper; its hook is Sec. 5.4: signed
+ * distances of non-spherical shapes cost more per lattice node).  For a shape
+ * family (HLBM_ROUNDED_CUBE or HLBM_SPHEROID with a fixed aspect) a network
+ * 3 -> 64 -> 64 -> 64 -> 1 with SiLU activations maps a body-frame point
+ * divided by the circumradius R_c to d_s / R_c.  BF16 matrix-core products
+ * with FP32 accumulation; FP32 master parameters trained with Adam.  When a
+ * family is in HLBM_INDICATOR_LEARNED mode, every step evaluates the network
+ * at the cells of each such particle's coupling box (a per-particle distance
+ * table) and both the indicator B(d_s) and the inside test d_s <= 0 of the
+ * momentum exchange use it.  Requires cfg.learned = 1.
+ *
+ * Parameters are one flat float vector of HLBM_MLP_NPARAM entries in the
+ * order W1 (64x3, row-major), b1 (64), W2 (64x64), b2, W3 (64x64), b3,
+ * W4 (64), b4 (1).
+ * ------------------------------------------------------------------------ */
+#define HLBM_MLP_NPARAM 8641
+#define HLBM_INDICATOR_EXACT 0
+#define HLBM_INDICATOR_LEARNED 1
+
+typedef struct hlbm_train_opts {
+    int32_t samples;     /* training samples, half uniform in the box, half within `band` */
+    int32_t holdout;     /* held-out samples within `band` (judge the gate) */
+    int32_t iterations;  /* Adam steps */
+    int32_t batch;       /* samples per step */
+    double lr;           /* initial learning rate */
+    double lr_final;     /* learning rate of the last step (geometric decay) */
+    double box;          /* sampling cube half-width, in circumradii (e.g. 1.1) */
+    double band;         /* near-surface band half-width, in circumradii */
+    double clip;         /* targets clipped to +-clip circumradii */
+    double gate_rms;     /* accept if held-out RMS error <= gate_rms ... */
+    double gate_max;     /* ... and max error <= gate_max (lattice units at ref size) */
+    double ref_circumradius; /* particle size (lattice units) at which the gate is judged */
+    uint64_t seed;       /* sample generator seed */
+} hlbm_train_opts;
+
+typedef struct hlbm_train_report {
+    double loss_first;   /* mean-squared loss (normalised units) of the first batch */
+    double loss_last;    /* ... and of the last batch */
+    double rms_err;      /* held-out RMS |d_net - d| in lattice units at ref size */
+    double max_err;      /* held-out max |d_net - d| in lattice units at ref size */
+    double train_ms;     /* wall time of sample generation + training */
+    int32_t iterations;
+    int32_t accepted;    /* 1: gate passed and the family switched to LEARNED */
+} hlbm_train_report;
+
+/* Load / read the network parameters of a shape family (host float arrays of
+ * HLBM_MLP_NPARAM).  Setting parameters resets the Adam moments. */
+int hlbm_mlp_set_params(hlbm_ctx *ctx, int32_t shape, const float *theta);
+int hlbm_mlp_get_params(hlbm_ctx *ctx, int32_t shape, float *theta);
+
+/* Network outputs at n normalised points pts[n][3] (host) -> out[n] (host). */
+int hlbm_mlp_eval(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts, double *out);
+
+/* Gradient of the mean-squared loss mean_s (net(pts_s) - target_s)^2 with
+ * respect to the parameters (host double[HLBM_MLP_NPARAM]) and the loss,
+ * computed by the training kernels (BF16 products, FP32 accumulation). */
+int hlbm_mlp_gradient(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts, const double *target,
+                      double *grad, double *loss);
+
+/* Train the family's network (starting from its current parameters) on
+ * samples of the exact signed distance of a shape with parameters param[3]
+ * (lattice units; they fix the aspect), generated on the GPU.  If the
+ * held-out errors pass the gate the family switches to LEARNED, otherwise it
+ * stays EXACT (the fallback).  Synchronises the stream. */
+int hlbm_train_indicator(hlbm_ctx *ctx, int32_t shape, const double *param, const hlbm_train_opts *opts,
+                         hlbm_train_report *report);
+
+/* Select HLBM_INDICATOR_EXACT or HLBM_INDICATOR_LEARNED for a shape family.
+ * LEARNED needs parameters (set or trained) and an aspect ratio: particles of
+ * the family whose aspect differs from the trained one keep the exact path. */
+int hlbm_set_indicator(hlbm_ctx *ctx, int32_t shape, int32_t mode);
 
 /* Number of particles currently held. */
 int hlbm_num_particles(const hlbm_ctx *ctx, int32_t *n);

@@ -11,6 +11,9 @@
 #include <vector>
 
 #include "hlbm_internal.h"
+#include "hlbm_mlp.h"
+
+#include <chrono>
 
 using namespace hlbm;
 
@@ -44,6 +47,9 @@ size_t pop_bytes(int precision) { return precision == HLBM_FP64 ? 8 : (precision
 
 struct Layout {
   size_t fA, fB, parts, stage_parts, tcnt[2], tlist[2], partial, status, stage, total;
+  // learned indicator (cfg.learned)
+  size_t theta[2], mom1[2], mom2[2], packed[2], gpart, gout, pool, epts, eout, tables;
+  long long pool_cap, table_cap;
 };
 
 int validate(const hlbm_config *c) {
@@ -59,6 +65,10 @@ int validate(const hlbm_config *c) {
   if (!(c->tau > 0.5) || !isfinite(c->tau)) return fail(HLBM_EINVAL, "tau must be > 1/2 (nu > 0)");
   if (!(c->eps > 0.0) || !isfinite(c->eps)) return fail(HLBM_EINVAL, "eps must be > 0");
   if (!isfinite(c->rho_f)) return fail(HLBM_EINVAL, "rho_f not finite");
+  if (c->learned != 0 && c->learned != 1) return fail(HLBM_EINVAL, "learned must be 0 or 1");
+  if (c->learned && !(c->learned_max_circumradius > 0 && c->learned_max_circumradius <= 27.0))
+    return fail(HLBM_EINVAL, "learned_max_circumradius must be in (0, 27]");
+  if (c->learned && c->learned_samples < 0) return fail(HLBM_EINVAL, "learned_samples < 0");
   for (int k = 0; k < 3; ++k)
     if (!isfinite(c->gravity[k]) || !isfinite(c->fluid_accel[k]))
       return fail(HLBM_EINVAL, "gravity / fluid_accel not finite");
@@ -78,6 +88,8 @@ Lattice make_lattice(const hlbm_config *c) {
   L.eps = c->eps;
   for (int k = 0; k < 3; ++k) { L.af[k] = c->fluid_accel[k]; L.g[k] = c->gravity[k]; }
   L.rho_f = c->rho_f;
+  L.tables = nullptr;
+  L.table_cap = 0;
   return L;
 }
 
@@ -97,6 +109,25 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
   y.partial = off; off += align_up(np * LMAX_CAP * 6 * sizeof(double));
   y.status = off; off += 256;
   y.stage = off; off += align_up((size_t)4 * L.N * sizeof(double));
+  y.pool_cap = 0;
+  y.table_cap = 0;
+  if (c->learned) {
+    for (int f = 0; f < 2; ++f) {
+      y.theta[f] = off; off += align_up(MLP_PARTIAL * sizeof(float));
+      y.mom1[f] = off; off += align_up(MLP_PARTIAL * sizeof(float));
+      y.mom2[f] = off; off += align_up(MLP_PARTIAL * sizeof(float));
+      y.packed[f] = off; off += align_up(MLP_PACKED * 2);
+    }
+    y.gpart = off; off += align_up((size_t)MLP_MAX_BLOCKS * MLP_PARTIAL * sizeof(float));
+    y.gout = off; off += align_up(MLP_PARTIAL * sizeof(float));
+    y.pool_cap = c->learned_samples > 0 ? c->learned_samples : 1200000;
+    y.pool = off; off += align_up((size_t)y.pool_cap * 16);
+    y.epts = off; off += align_up((size_t)y.pool_cap * 3 * sizeof(float));
+    y.eout = off; off += align_up((size_t)y.pool_cap * sizeof(float));
+    const long long side = (long long)floor(2.0 * (c->learned_max_circumradius + 0.5 * c->eps)) + 2;
+    y.table_cap = side * side * side;
+    y.tables = off; off += align_up((size_t)np * y.table_cap * sizeof(float));
+  }
   y.total = off + 256;  // slack for aligning the caller's base pointer
   return y;
 }
@@ -123,6 +154,15 @@ struct hlbm_ctx {
   bool profiling;
   std::vector<hipEvent_t> events;  // start/stop pairs around collide launches
   size_t events_used;
+  // learned indicator, index 0: rounded cube, 1: spheroid
+  float *theta[2], *mom1[2], *mom2[2];
+  __bf16 *packed[2];
+  float *gpart, *gout, *epts, *eout;
+  float4 *pool;
+  float *tables;
+  int mode[2];        // HLBM_INDICATOR_EXACT / LEARNED
+  int has_params[2];
+  double aspect[2];   // param[1] / param[0] of the trained shape, 0 = unknown
 };
 
 namespace {
@@ -140,6 +180,24 @@ int check_status(hlbm_ctx *c) {
     return fail(HLBM_EUNSTABLE, "non-finite or non-positive density, or |u| > 0.3");
   }
   return HLBM_OK;
+}
+
+bool any_learned(const hlbm_ctx *c) {
+  return c->tables && (c->mode[0] == HLBM_INDICATOR_LEARNED || c->mode[1] == HLBM_INDICATOR_LEARNED);
+}
+
+int refresh_tables(hlbm_ctx *c) {
+  if (!any_learned(c) || c->n == 0) return HLBM_OK;
+  HIP_TRY(launch_mlp_table(c->L, c->parts, c->n, c->theta[0], c->packed[0], c->theta[1], c->packed[1], c->tables,
+                           c->lay.table_cap, c->stream));
+  return HLBM_OK;
+}
+
+int mark_learned(hlbm_ctx *c) {
+  if (!c->tables || c->n == 0) return HLBM_OK;
+  HIP_TRY(launch_mark_learned(c->parts, c->n, c->mode[0] == HLBM_INDICATOR_LEARNED, c->aspect[0],
+                              c->mode[1] == HLBM_INDICATOR_LEARNED, c->aspect[1], c->stream));
+  return refresh_tables(c);
 }
 
 int rebin(hlbm_ctx *c) {
@@ -206,6 +264,31 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   c->steps_done = 0;
   c->profiling = false;
   c->events_used = 0;
+  for (int f = 0; f < 2; ++f) {
+    c->theta[f] = c->mom1[f] = c->mom2[f] = nullptr;
+    c->packed[f] = nullptr;
+    c->mode[f] = HLBM_INDICATOR_EXACT;
+    c->has_params[f] = 0;
+    c->aspect[f] = 0.0;
+  }
+  c->gpart = c->gout = c->epts = c->eout = c->tables = nullptr;
+  c->pool = nullptr;
+  if (cfg->learned) {
+    for (int f = 0; f < 2; ++f) {
+      c->theta[f] = (float *)(c->base + lay.theta[f]);
+      c->mom1[f] = (float *)(c->base + lay.mom1[f]);
+      c->mom2[f] = (float *)(c->base + lay.mom2[f]);
+      c->packed[f] = (__bf16 *)(c->base + lay.packed[f]);
+    }
+    c->gpart = (float *)(c->base + lay.gpart);
+    c->gout = (float *)(c->base + lay.gout);
+    c->pool = (float4 *)(c->base + lay.pool);
+    c->epts = (float *)(c->base + lay.epts);
+    c->eout = (float *)(c->base + lay.eout);
+    c->tables = (float *)(c->base + lay.tables);
+    c->L.tables = c->tables;
+    c->L.table_cap = lay.table_cap;
+  }
   // rest state: every deviation f_i - w_i is zero
   hipError_t e = hipMemsetAsync(c->fA, 0, (size_t)19 * L.N * pop_bytes(cfg->precision), c->stream);
   if (e == hipSuccess) e = launch_fill_int(c->tcnt[0], 0, L.ntiles, c->stream);
@@ -310,6 +393,8 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
     const int tiles_z = std::min(ctx->L.ntz, cells / TZ + 2);
     cap = std::max(cap, tiles_x * tiles_y * tiles_z);
     lmax = std::max(lmax, (int)floor(2.0 * rc) + 2);
+    if (ctx->cfg.learned && p.shape != HLBM_SPHERE && rc > ctx->cfg.learned_max_circumradius)
+      return fail(HLBM_EINVAL, "particle %d: circumradius %.3f above learned_max_circumradius", i, rc);
   }
   if (lmax > LMAX_CAP) return fail(HLBM_EUNSUPPORTED, "circumradius too large");
   HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -321,6 +406,8 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
   ctx->bin_cap = cap;
   ctx->lmax = lmax;
   int rc = rebin(ctx);
+  if (rc) return rc;
+  rc = mark_learned(ctx);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return check_status(ctx);
@@ -357,6 +444,8 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
       HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->n, ctx->lmax, ctx->partial, s));
       HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, ctx->partial, ctx->tcnt[nxt],
                              ctx->tlist[nxt], ctx->status, s));
+      int rc = refresh_tables(ctx);
+      if (rc) return rc;
     }
     const int use = ctx->n > 0 ? nxt : ctx->cur;
     int *clear = ctx->n > 0 ? ctx->tcnt[ctx->cur] : nullptr;
@@ -444,6 +533,185 @@ int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_de
   }
   (void)planes;
   return check_status(ctx);
+}
+
+
+// ---------------------------------------------------------------------------
+// Learned indicator
+// ---------------------------------------------------------------------------
+static int family(hlbm_ctx *ctx, int32_t shape, int *f) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  if (!ctx->cfg.learned) return fail(HLBM_ESTATE, "the context was created without cfg.learned");
+  if (shape != HLBM_ROUNDED_CUBE && shape != HLBM_SPHEROID)
+    return fail(HLBM_EINVAL, "learned indicators exist for HLBM_ROUNDED_CUBE and HLBM_SPHEROID");
+  *f = shape == HLBM_ROUNDED_CUBE ? 0 : 1;
+  return HLBM_OK;
+}
+
+static double circumradius_host(int shape, const double *prm) {
+  if (shape == HLBM_ROUNDED_CUBE) return sqrt(3.0) * (prm[0] - prm[1]) + prm[1];
+  if (shape == HLBM_SPHEROID) return fmax(prm[0], prm[1]);
+  return prm[0];
+}
+
+int hlbm_mlp_set_params(hlbm_ctx *ctx, int32_t shape, const float *theta) {
+  int f, rc = family(ctx, shape, &f);
+  if (rc) return rc;
+  if (!theta) return fail(HLBM_EINVAL, "theta is NULL");
+  for (int k = 0; k < MLP_NPARAM; ++k)
+    if (!isfinite(theta[k])) return fail(HLBM_EINVAL, "theta[%d] not finite", k);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(hipMemcpyAsync(ctx->theta[f], theta, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(launch_fill_int((int *)ctx->mom1[f], 0, MLP_PARTIAL, ctx->stream));
+  HIP_TRY(launch_fill_int((int *)ctx->mom2[f], 0, MLP_PARTIAL, ctx->stream));
+  HIP_TRY(mlp_pack(ctx->theta[f], ctx->packed[f], ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->has_params[f] = 1;
+  return refresh_tables(ctx);
+}
+
+int hlbm_mlp_get_params(hlbm_ctx *ctx, int32_t shape, float *theta) {
+  int f, rc = family(ctx, shape, &f);
+  if (rc) return rc;
+  if (!theta) return fail(HLBM_EINVAL, "theta is NULL");
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(hipMemcpy(theta, ctx->theta[f], sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
+  return HLBM_OK;
+}
+
+int hlbm_mlp_eval(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts, double *out) {
+  int f, rc = family(ctx, shape, &f);
+  if (rc) return rc;
+  if (n < 0 || n > ctx->lay.pool_cap) return fail(HLBM_EINVAL, "n outside [0, %lld]", ctx->lay.pool_cap);
+  if (n == 0) return HLBM_OK;
+  if (!pts || !out) return fail(HLBM_EINVAL, "NULL buffer");
+  if (!ctx->has_params[f]) return fail(HLBM_ESTATE, "no parameters for this family");
+  std::vector<float> p((size_t)3 * n), o(n);
+  for (long long k = 0; k < 3LL * n; ++k) p[k] = (float)pts[k];
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(hipMemcpyAsync(ctx->epts, p.data(), sizeof(float) * 3 * n, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(mlp_eval(ctx->theta[f], ctx->packed[f], ctx->epts, ctx->eout, n, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(o.data(), ctx->eout, sizeof(float) * n, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < n; ++k) out[k] = o[k];
+  return HLBM_OK;
+}
+
+int hlbm_mlp_gradient(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts, const double *target,
+                      double *grad, double *loss) {
+  int f, rc = family(ctx, shape, &f);
+  if (rc) return rc;
+  if (n < 1 || n > ctx->lay.pool_cap) return fail(HLBM_EINVAL, "n outside [1, %lld]", ctx->lay.pool_cap);
+  if (!pts || !target || !grad) return fail(HLBM_EINVAL, "NULL buffer");
+  if (!ctx->has_params[f]) return fail(HLBM_ESTATE, "no parameters for this family");
+  std::vector<float4> smp(n);
+  for (int k = 0; k < n; ++k)
+    smp[k] = make_float4((float)pts[3 * k], (float)pts[3 * k + 1], (float)pts[3 * k + 2], (float)target[k]);
+  std::vector<float> g(MLP_PARTIAL);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(hipMemcpyAsync(ctx->pool, smp.data(), sizeof(float4) * n, hipMemcpyHostToDevice, ctx->stream));
+  const int nb = mlp_grad_blocks(n, MLP_MAX_BLOCKS);
+  HIP_TRY(mlp_grad(ctx->theta[f], ctx->packed[f], ctx->pool, n, MLP_MAX_BLOCKS, 2.0f / n, ctx->gpart, ctx->stream));
+  HIP_TRY(mlp_reduce_adam(ctx->theta[f], ctx->mom1[f], ctx->mom2[f], ctx->gpart, nb, ctx->gout, 0, 0.f, 1,
+                          ctx->stream));
+  HIP_TRY(hipMemcpyAsync(g.data(), ctx->gout, sizeof(float) * MLP_PARTIAL, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < MLP_NPARAM; ++k) grad[k] = g[k];
+  if (loss) *loss = g[MLP_NPARAM] / n;
+  return HLBM_OK;
+}
+
+int hlbm_train_indicator(hlbm_ctx *ctx, int32_t shape, const double *param, const hlbm_train_opts *o,
+                         hlbm_train_report *rep) {
+  int f, rc = family(ctx, shape, &f);
+  if (rc) return rc;
+  if (!param || !o) return fail(HLBM_EINVAL, "NULL argument");
+  if (!ctx->has_params[f]) return fail(HLBM_ESTATE, "set initial parameters first (hlbm_mlp_set_params)");
+  if (!(param[0] > 0 && param[1] > 0) || (shape == HLBM_ROUNDED_CUBE && param[1] > param[0]))
+    return fail(HLBM_EINVAL, "bad shape parameters");
+  if (o->samples < 64 || o->holdout < 1 || (long long)o->samples + o->holdout > ctx->lay.pool_cap)
+    return fail(HLBM_EINVAL, "samples + holdout must fit the sample capacity %lld", ctx->lay.pool_cap);
+  if (o->batch < 32 || o->batch > o->samples || o->iterations < 1)
+    return fail(HLBM_EINVAL, "need 32 <= batch <= samples and iterations >= 1");
+  if (!(o->lr > 0 && o->lr_final > 0 && o->box > 0 && o->band > 0 && o->clip >= o->band))
+    return fail(HLBM_EINVAL, "bad learning rate / box / band / clip");
+  const auto t0 = std::chrono::steady_clock::now();
+  const double Rc = circumradius_host(shape, param);
+  const double p0 = param[0] / Rc, p1 = param[1] / Rc;
+  hipStream_t s = ctx->stream;
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(mlp_samples(shape, p0, p1, o->seed, o->samples, o->box, o->band, o->clip, 0, ctx->pool, s));
+  HIP_TRY(mlp_samples(shape, p0, p1, o->seed ^ 0x5bd1e995ull, o->holdout, o->box, o->band, o->clip, 1,
+                      ctx->pool + o->samples, s));
+  HIP_TRY(launch_fill_int((int *)ctx->mom1[f], 0, MLP_PARTIAL, s));
+  HIP_TRY(launch_fill_int((int *)ctx->mom2[f], 0, MLP_PARTIAL, s));
+  const int nbatches = o->samples / o->batch;
+  const int nb = mlp_grad_blocks(o->batch, MLP_MAX_BLOCKS);
+  double loss_first = 0, loss_last = 0;
+  for (int it = 0; it < o->iterations; ++it) {
+    const double frac = o->iterations > 1 ? (double)it / (o->iterations - 1) : 0.0;
+    const float lr = (float)(o->lr * pow(o->lr_final / o->lr, frac));
+    const float4 *batch = ctx->pool + (size_t)(it % nbatches) * o->batch;
+    const bool record = it == 0 || it == o->iterations - 1;
+    HIP_TRY(mlp_grad(ctx->theta[f], ctx->packed[f], batch, o->batch, MLP_MAX_BLOCKS, 2.0f / o->batch, ctx->gpart, s));
+    HIP_TRY(mlp_reduce_adam(ctx->theta[f], ctx->mom1[f], ctx->mom2[f], ctx->gpart, nb, record ? ctx->gout : nullptr,
+                            1, lr, it + 1, s));
+    HIP_TRY(mlp_pack(ctx->theta[f], ctx->packed[f], s));
+    if (record) {
+      float sse = 0;
+      HIP_TRY(hipMemcpyAsync(&sse, ctx->gout + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      (it == 0 ? loss_first : loss_last) = sse / o->batch;
+    }
+  }
+  // held-out band samples
+  std::vector<float4> hold(o->holdout);
+  HIP_TRY(hipMemcpyAsync(hold.data(), ctx->pool + o->samples, sizeof(float4) * o->holdout, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<float> pts((size_t)3 * o->holdout), out(o->holdout);
+  for (int k = 0; k < o->holdout; ++k) {
+    pts[3 * k] = hold[k].x; pts[3 * k + 1] = hold[k].y; pts[3 * k + 2] = hold[k].z;
+  }
+  HIP_TRY(hipMemcpyAsync(ctx->epts, pts.data(), sizeof(float) * pts.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(mlp_eval(ctx->theta[f], ctx->packed[f], ctx->epts, ctx->eout, o->holdout, s));
+  HIP_TRY(hipMemcpyAsync(out.data(), ctx->eout, sizeof(float) * o->holdout, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double ref = o->ref_circumradius > 0 ? o->ref_circumradius : Rc;
+  double se = 0, mx = 0;
+  for (int k = 0; k < o->holdout; ++k) {
+    const double e = fabs((double)out[k] - (double)hold[k].w) * ref;
+    se += e * e;
+    mx = fmax(mx, e);
+  }
+  const double rms = sqrt(se / o->holdout);
+  const bool ok = isfinite(rms) && rms <= o->gate_rms && mx <= o->gate_max;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) {
+    rep->loss_first = loss_first;
+    rep->loss_last = loss_last;
+    rep->rms_err = rms;
+    rep->max_err = mx;
+    rep->train_ms = ms;
+    rep->iterations = o->iterations;
+    rep->accepted = ok ? 1 : 0;
+  }
+  ctx->aspect[f] = param[1] / param[0];
+  ctx->mode[f] = ok ? HLBM_INDICATOR_LEARNED : HLBM_INDICATOR_EXACT;
+  return mark_learned(ctx);
+}
+
+int hlbm_set_indicator(hlbm_ctx *ctx, int32_t shape, int32_t mode) {
+  int f, rc = family(ctx, shape, &f);
+  if (rc) return rc;
+  if (mode != HLBM_INDICATOR_EXACT && mode != HLBM_INDICATOR_LEARNED) return fail(HLBM_EINVAL, "bad mode");
+  if (mode == HLBM_INDICATOR_LEARNED && (!ctx->has_params[f] || !(ctx->aspect[f] > 0)))
+    return fail(HLBM_ESTATE, "the family has no trained network (hlbm_train_indicator)");
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->mode[f] = mode;
+  rc = mark_learned(ctx);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return HLBM_OK;
 }
 
 }  // extern "C"

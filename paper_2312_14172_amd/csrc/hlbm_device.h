@@ -44,6 +44,8 @@ struct Lattice {
   double af[3];   // fluid body acceleration
   double rho_f;
   double g[3];
+  const float *tables;  // per-particle learned distance tables (NULL: none)
+  long long table_cap;  // floats per particle table
 };
 
 // Particle record on the device (FP64).  The first block mirrors the public
@@ -57,7 +59,19 @@ struct DevParticle {
   double Th[3];    // hydrodynamic torque of the last momentum exchange
   int shape, flags;
   int lo[3], hi[3];  // cells that can have B > 0 (centre within rc + eps/2), unwrapped
+  int learned;       // 1: d_s comes from the particle's learned distance table
 };
+
+// Offset of a cell inside a particle's coupling box (wrapped on periodic axes);
+// the table index is lx + sx (ly + sy lz).
+__device__ inline int box_offset(int v, int lo, int n, int periodic) {
+  int d = v - lo;
+  if (periodic) {
+    if (d < 0) d += n;
+    else if (d >= n) d -= n;
+  }
+  return d;
+}
 
 // ---------------------------------------------------------------------------
 // Population storage.  All formats hold the deviation g_i = f_i - w_i.

@@ -103,8 +103,23 @@ __global__ void k_prepare(Lattice L, const hlbm_particle *in, DevParticle *out, 
   p.V = s.volume;
   p.shape = s.shape;
   p.flags = s.flags;
+  p.learned = 0;
   derive(L, p);
   out[i] = p;
+}
+
+// Mark the particles whose shape family uses its learned indicator (and whose
+// aspect matches the trained one).
+__global__ void k_mark_learned(DevParticle *parts, int n, int mode_cube, double aspect_cube, int mode_sph,
+                               double aspect_sph) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  DevParticle &p = parts[i];
+  const double asp = p.prm[1] / p.prm[0];
+  int on = 0;
+  if (p.shape == 1 && mode_cube) on = fabs(asp - aspect_cube) <= 1e-6 * aspect_cube;
+  if (p.shape == 2 && mode_sph) on = fabs(asp - aspect_sph) <= 1e-6 * aspect_sph;
+  p.learned = on;
 }
 
 __global__ void k_fill_int(int *p, int v, int n) {
@@ -224,6 +239,8 @@ __global__ __launch_bounds__(256) void k_mea(Lattice L, const typename ST::S *__
   double R[9];
   for (int k = 0; k < 9; ++k) R[k] = sp.R[k];
   const int sx = hi[0] - lo[0] + 1, sy = hi[1] - lo[1] + 1;
+  const int learned = sp.learned && L.tables;
+  const int tsx = sp.hi[0] - sp.lo[0] + 1, tsy = sp.hi[1] - sp.lo[1] + 1;
   const int nn[3] = {L.nx, L.ny, L.nz};
   double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
   for (int idx = threadIdx.x; idx < sx * sy; idx += blockDim.x) {
@@ -242,13 +259,22 @@ __global__ __launch_bounds__(256) void k_mea(Lattice L, const typename ST::S *__
       }
       d[k] = dv;
     }
-    double b[3] = {d[0], d[1], d[2]};
-    if (shape != 0) {
-      b[0] = R[0] * d[0] + R[3] * d[1] + R[6] * d[2];
-      b[1] = R[1] * d[0] + R[4] * d[1] + R[7] * d[2];
-      b[2] = R[2] * d[0] + R[5] * d[1] + R[8] * d[2];
+    bool in;
+    if (learned) {
+      const int lx = box_offset(c[0], sp.lo[0], L.nx, !L.bc[0]);
+      const int ly = box_offset(c[1], sp.lo[1], L.ny, !L.bc[1]);
+      const int lz = box_offset(c[2], sp.lo[2], L.nz, !L.bc[2]);
+      in = L.tables[(size_t)pid * L.table_cap + lx + tsx * (ly + tsy * lz)] <= 0.0f;
+    } else {
+      double b[3] = {d[0], d[1], d[2]};
+      if (shape != 0) {
+        b[0] = R[0] * d[0] + R[3] * d[1] + R[6] * d[2];
+        b[1] = R[1] * d[0] + R[4] * d[1] + R[7] * d[2];
+        b[2] = R[2] * d[0] + R[5] * d[1] + R[8] * d[2];
+      }
+      in = inside_body(shape, p0, p1, b[0], b[1], b[2]);
     }
-    if (!inside_body(shape, p0, p1, b[0], b[1], b[2])) continue;
+    if (!in) continue;
     const double upx = U[0] + W[1] * d[2] - W[2] * d[1];
     const double upy = U[1] + W[2] * d[0] - W[0] * d[2];
     const double upz = U[2] + W[0] * d[1] - W[1] * d[0];
@@ -394,6 +420,8 @@ struct Cand {
   int Xi[3];     // floor(X)
   int lo[3], hi[3];
   int shape;
+  long long tab; // first table entry of a learned particle, -1 for the exact path
+  int tsx, tsy;  // coupling-box extents (table strides)
 };
 
 template <typename G>
@@ -436,6 +464,9 @@ __device__ inline void load_candidates(const Lattice &L, const DevParticle *part
     const double ri = fmax(p.prm[0] - 0.5 * L.eps, 0.0);
     c.inner2 = (p.shape == 0) ? (G)(ri * ri) : G(-1);
     c.shape = p.shape;
+    c.tab = (p.learned && L.tables) ? (long long)id * L.table_cap : -1;
+    c.tsx = p.hi[0] - p.lo[0] + 1;
+    c.tsy = p.hi[1] - p.lo[1] + 1;
   }
   __syncthreads();
 }
@@ -482,7 +513,12 @@ __device__ inline void coupling_at(const Lattice &L, const TileCands<G> &tc, con
     const G r2 = d0 * d0 + d1 * d1 + d2 * d2;
     if (!(r2 < c.reach2)) continue;
     G Bp;
-    if (c.shape == 0) {
+    if (c.tab >= 0) {
+      const int lx = box_offset(cp.x, c.lo[0], L.nx, !L.bc[0]);
+      const int ly = box_offset(cp.y, c.lo[1], L.ny, !L.bc[1]);
+      const int lz = box_offset(cp.z, c.lo[2], L.nz, !L.bc[2]);
+      Bp = indicator<G>((G)L.tables[c.tab + lx + c.tsx * (ly + c.tsy * lz)], eps);
+    } else if (c.shape == 0) {
       Bp = (r2 <= c.inner2) ? G(1) : indicator<G>(dsqrt(r2) - c.p0, eps);
     } else {
       const G b0 = c.R[0] * d0 + c.R[3] * d1 + c.R[6] * d2;
@@ -700,6 +736,14 @@ static inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b)
 hipError_t launch_prepare(const Lattice &L, const hlbm_particle *in, DevParticle *out, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_prepare, dim3(blocks_for(n, 128)), dim3(128), 0, s, L, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_learned(DevParticle *parts, int n, int mode_cube, double aspect_cube, int mode_sph,
+                               double aspect_sph, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_learned, dim3(blocks_for(n, 128)), dim3(128), 0, s, parts, n, mode_cube, aspect_cube,
+                     mode_sph, aspect_sph);
   return hipGetLastError();
 }
 

@@ -1,0 +1,449 @@
+// hlbm_mlp.hip -- BF16 matrix-core kernels of the signed-distance surrogate
+// network used by the learned indicator (3 -> 64 -> 64 -> 64 -> 1, SiLU):
+// exact-SDF training samples, forward + back-propagation, Adam, inference.
+//
+// Matrix products run on v_mfma_f32_16x16x32_bf16 in a transposed form:
+// activations are kept as H^T (features x samples), one 16-sample tile per
+// MFMA column block.  In that form a layer's accumulator layout (lane l holds
+// rows 4(l/16)..4(l/16)+3 of a 16-row tile, column l%16) is already the B
+// operand layout of the next layer's product once the contraction index is
+// permuted: within a 32-feature chunk c, lane group g = l/16 and element
+// e = 0..7 stand for feature kappa(c, g, e) = 32c + 4g + (e & 3) + 16 (e >> 2).
+// The weight matrices are stored pre-permuted in that order, so no data moves
+// between layers.  Weight-gradient products (contraction over samples) go
+// through LDS to transpose activations and errors.
+#include "hlbm_device.h"
+#include "hlbm_mlp.h"
+
+namespace hlbm {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline int kappa(int c, int g, int e) { return 32 * c + 4 * g + (e & 3) + 16 * (e >> 2); }
+
+__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float dsilu_f(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+__device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// 16 C-layout values of a 64-feature column (index ot*4 + j = feature
+// 16 ot + 4 g + j) -> the two bf16x8 B operands of chunks c = 0, 1.
+__device__ inline void pack_b(const float *v, bf16x8 *b) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b[c][e] = (__bf16)v[(2 * c + (e >> 2)) * 4 + (e & 3)];
+}
+
+// ---------------------------------------------------------------------------
+// Weight packing (after every parameter update)
+// ---------------------------------------------------------------------------
+// wf[L][(ot*2 + c)*64 + lane][e] = W_L[16 ot + lane%16][kappa(c, lane/16, e)]  (forward, A = W)
+// wb[L][(kt*2 + c)*64 + lane][e] = W_L[kappa(c, lane/16, e)][16 kt + lane%16]  (backward, A = W^T)
+__global__ void k_mlp_pack(const float *__restrict__ theta, __bf16 *__restrict__ packed) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. 4 * 4096
+  if (t >= 4 * 4096) return;
+  const int which = t / 4096;  // 0: wf2, 1: wf3, 2: wb2, 3: wb3
+  const int r = t % 4096;
+  const int e = r % 8, lane = (r / 8) % 64, c = (r / 512) % 2, tile = r / 1024;
+  const float *W = theta + ((which & 1) ? MLP_OFF_W3 : MLP_OFF_W2);
+  const int g = lane / 16, li = lane % 16;
+  const int k = kappa(c, g, e);
+  float v;
+  if (which < 2) v = W[(16 * tile + li) * 64 + k];
+  else v = W[k * 64 + 16 * tile + li];
+  packed[t] = (__bf16)v;
+}
+
+struct MlpArgs {
+  const float *theta;
+  const bf16x8 *wf2, *wf3, *wb2, *wb3;
+};
+
+__device__ inline MlpArgs mlp_args(const float *theta, const __bf16 *packed) {
+  MlpArgs a;
+  a.theta = theta;
+  a.wf2 = (const bf16x8 *)(packed);
+  a.wf3 = (const bf16x8 *)(packed + 4096);
+  a.wb2 = (const bf16x8 *)(packed + 2 * 4096);
+  a.wb3 = (const bf16x8 *)(packed + 3 * 4096);
+  return a;
+}
+
+// Forward pass of one 16-sample tile held by the wave: lane l holds sample
+// l%16's input.  Outputs the pre-activations z1..z3 (C layout, 16 per lane)
+// and y (replicated over the four lanes of each sample).
+__device__ inline void mlp_forward_tile(const MlpArgs &A, float x0, float x1, float x2, float *z1, float *z2,
+                                        float *z3, float &y) {
+  const int l = threadIdx.x & 63, g = l >> 4;
+  const float *th = A.theta;
+  float h[16];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int f = 16 * ot + 4 * g + j;
+      const float z = th[MLP_OFF_B1 + f] + th[MLP_OFF_W1 + 3 * f] * x0 + th[MLP_OFF_W1 + 3 * f + 1] * x1 +
+                      th[MLP_OFF_W1 + 3 * f + 2] * x2;
+      z1[ot * 4 + j] = z;
+      h[ot * 4 + j] = silu_f(z);
+    }
+  bf16x8 b[2];
+  pack_b(h, b);
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma(A.wf2[(ot * 2 + 0) * 64 + l], b[0], acc);
+    acc = mfma(A.wf2[(ot * 2 + 1) * 64 + l], b[1], acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z2[ot * 4 + j] = acc[j] + th[MLP_OFF_B2 + 16 * ot + 4 * g + j];
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) h[k] = silu_f(z2[k]);
+  pack_b(h, b);
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma(A.wf3[(ot * 2 + 0) * 64 + l], b[0], acc);
+    acc = mfma(A.wf3[(ot * 2 + 1) * 64 + l], b[1], acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z3[ot * 4 + j] = acc[j] + th[MLP_OFF_B3 + 16 * ot + 4 * g + j];
+  }
+  float part = 0.f;
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part += th[MLP_OFF_W4 + 16 * ot + 4 * g + j] * silu_f(z3[ot * 4 + j]);
+  part += __shfl_xor(part, 16, 64);
+  part += __shfl_xor(part, 32, 64);
+  y = part + th[MLP_OFF_B4];
+}
+
+// ---------------------------------------------------------------------------
+// Inference: out[i] = network(pts[i]) for n points (normalised body frame).
+// One wave per 64 points (four 16-point tiles).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_mlp_eval(const float *__restrict__ theta, const __bf16 *__restrict__ packed,
+                                                 const float *__restrict__ pts, float *__restrict__ out, int n) {
+  const MlpArgs A = mlp_args(theta, packed);
+  const int l = threadIdx.x, g = l >> 4;
+  for (int q = 0; q < 4; ++q) {
+    const int s = blockIdx.x * 64 + q * 16 + (l & 15);
+    const bool ok = s < n;
+    const float x0 = ok ? pts[3 * s] : 0.f, x1 = ok ? pts[3 * s + 1] : 0.f, x2 = ok ? pts[3 * s + 2] : 0.f;
+    float z1[16], z2[16], z3[16], y;
+    mlp_forward_tile(A, x0, x1, x2, z1, z2, z3, y);
+    if (ok && g == 0) out[s] = y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient of the mean-squared loss over a batch.  One wave per workgroup;
+// workgroup b handles samples [b*per, (b+1)*per) in pairs of 16-sample tiles
+// and writes its partial gradient (MLP_NPARAM floats) and squared-error sum.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ theta, const __bf16 *__restrict__ packed,
+                                                 const float4 *__restrict__ samples, int n, int per, float scale,
+                                                 float *__restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) __bf16 hT1[64][32], hT2[64][32], dT2[64][32], dT3[64][32];
+  const MlpArgs A = mlp_args(theta, packed);
+  const float *th = theta;
+  const int l = threadIdx.x, g = l >> 4, li = l & 15;
+  float gW1[16][3], gb1[16], gb2[16], gb3[16], gW4[16], gb4 = 0.f, sse = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    gW1[k][0] = gW1[k][1] = gW1[k][2] = 0.f;
+    gb1[k] = gb2[k] = gb3[k] = gW4[k] = 0.f;
+  }
+  f32x4 dW2[4][4], dW3[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      dW2[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      dW3[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  const int s0 = blockIdx.x * per;
+  const int s1 = min(n, s0 + per);
+  for (int base = s0; base < s1; base += 32) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int s = base + q * 16 + li;
+      const bool ok = s < s1;
+      const float4 smp = ok ? samples[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float z1[16], z2[16], z3[16], y;
+      mlp_forward_tile(A, smp.x, smp.y, smp.z, z1, z2, z3, y);
+      const float err = ok ? (y - smp.w) : 0.f;
+      if (g == 0) sse += err * err;
+      const float dy = scale * err;
+      if (g == 0) gb4 += dy;
+      // layer 4 and the error entering layer 3
+      float d[16];
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = ot * 4 + j, f = 16 * ot + 4 * g + j;
+          gW4[k] += dy * silu_f(z3[k]);
+          d[k] = th[MLP_OFF_W4 + f] * dy * dsilu_f(z3[k]);
+          gb3[k] += d[k];
+          dT3[f][q * 16 + li] = (__bf16)d[k];
+          hT2[f][q * 16 + li] = (__bf16)silu_f(z2[k]);
+        }
+      // error entering layer 2: W3^T d3
+      bf16x8 b[2];
+      pack_b(d, b);
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(A.wb3[(kt * 2 + 0) * 64 + l], b[0], acc);
+        acc = mfma(A.wb3[(kt * 2 + 1) * 64 + l], b[1], acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = kt * 4 + j, f = 16 * kt + 4 * g + j;
+          d[k] = acc[j] * dsilu_f(z2[k]);
+          gb2[k] += d[k];
+          dT2[f][q * 16 + li] = (__bf16)d[k];
+          hT1[f][q * 16 + li] = (__bf16)silu_f(z1[k]);
+        }
+      }
+      // error entering layer 1: W2^T d2
+      pack_b(d, b);
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(A.wb2[(kt * 2 + 0) * 64 + l], b[0], acc);
+        acc = mfma(A.wb2[(kt * 2 + 1) * 64 + l], b[1], acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = kt * 4 + j;
+          const float d1 = acc[j] * dsilu_f(z1[k]);
+          gb1[k] += d1;
+          gW1[k][0] += d1 * smp.x;
+          gW1[k][1] += d1 * smp.y;
+          gW1[k][2] += d1 * smp.z;
+        }
+      }
+    }
+    // weight gradients of the two 64x64 layers: contraction over the 32
+    // samples of the pair, operands transposed through LDS
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const bf16x8 a3 = *(const bf16x8 *)&dT3[16 * a + li][8 * g];
+      const bf16x8 a2 = *(const bf16x8 *)&dT2[16 * a + li][8 * g];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const bf16x8 b2 = *(const bf16x8 *)&hT2[16 * b + li][8 * g];
+        const bf16x8 b1 = *(const bf16x8 *)&hT1[16 * b + li][8 * g];
+        dW3[a][b] = mfma(a3, b2, dW3[a][b]);
+        dW2[a][b] = mfma(a2, b1, dW2[a][b]);
+      }
+    }
+    __syncthreads();
+  }
+  // ---- write this workgroup's partial gradient ------------------------
+  float *out = partial + (size_t)blockIdx.x * MLP_PARTIAL;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * a + 4 * g + j, col = 16 * b + li;
+        out[MLP_OFF_W2 + row * 64 + col] = dW2[a][b][j];
+        out[MLP_OFF_W3 + row * 64 + col] = dW3[a][b][j];
+      }
+  // per-feature sums over the 16 sample lanes of each lane group
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    float v[7] = {gb1[k], gb2[k], gb3[k], gW4[k], gW1[k][0], gW1[k][1], gW1[k][2]};
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      v[m] += __shfl_xor(v[m], 1, 64);
+      v[m] += __shfl_xor(v[m], 2, 64);
+      v[m] += __shfl_xor(v[m], 4, 64);
+      v[m] += __shfl_xor(v[m], 8, 64);
+    }
+    if (li == 0) {
+      const int f = 16 * (k / 4) + 4 * g + (k % 4);
+      out[MLP_OFF_B1 + f] = v[0];
+      out[MLP_OFF_B2 + f] = v[1];
+      out[MLP_OFF_B3 + f] = v[2];
+      out[MLP_OFF_W4 + f] = v[3];
+      out[MLP_OFF_W1 + 3 * f + 0] = v[4];
+      out[MLP_OFF_W1 + 3 * f + 1] = v[5];
+      out[MLP_OFF_W1 + 3 * f + 2] = v[6];
+    }
+  }
+  float v4[2] = {gb4, sse};
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v4[m] += __shfl_xor(v4[m], off, 64);
+  if (l == 0) {
+    out[MLP_OFF_B4] = v4[0];
+    out[MLP_NPARAM] = v4[1];
+  }
+}
+
+// Sum the workgroup partials in a fixed order; optionally apply one Adam step
+// (Kingma & Ba 2015, bias-corrected) to the FP32 master parameters.
+__global__ void k_mlp_reduce_adam(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
+                                  const float *__restrict__ partial, int nblocks, float *__restrict__ grad_out,
+                                  int do_step, float lr, float b1, float b2, float eps, float bc1, float bc2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > MLP_NPARAM) return;
+  float gsum = 0.f;
+  for (int b = 0; b < nblocks; ++b) gsum += partial[(size_t)b * MLP_PARTIAL + p];
+  if (grad_out) grad_out[p] = gsum;
+  if (!do_step || p == MLP_NPARAM) return;
+  const float mn = b1 * m[p] + (1.f - b1) * gsum;
+  const float vn = b2 * v[p] + (1.f - b2) * gsum * gsum;
+  m[p] = mn;
+  v[p] = vn;
+  theta[p] -= lr * (mn / bc1) / (sqrtf(vn / bc2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Training samples from the exact signed distance (normalised units: the
+// shape is scaled to circumradius 1).  Counter-based random numbers
+// (splitmix64 of seed and sample index).  Even samples are uniform in
+// [-box, box]^3; odd samples are drawn until |d| <= band (at most 64 tries).
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__device__ inline double uniform01(uint64_t seed, uint64_t idx, int k) {
+  return (double)(splitmix64(seed ^ splitmix64(idx * 64 + (uint64_t)k)) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+__global__ void k_sdf_samples(int shape, double p0, double p1, uint64_t seed, int n, double box, double band,
+                              double clip, int band_only, float4 *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool want_band = band_only || (i & 1);
+  double x = 0, y = 0, z = 0, d = 0;
+  for (int k = 0; k < 64; ++k) {
+    x = (2.0 * uniform01(seed, i, 3 * k) - 1.0) * box;
+    y = (2.0 * uniform01(seed, i, 3 * k + 1) - 1.0) * box;
+    z = (2.0 * uniform01(seed, i, 3 * k + 2) - 1.0) * box;
+    d = sdf_body<double>(shape, p0, p1, x, y, z);
+    if (!want_band || fabs(d) <= band) break;
+  }
+  const double t = fmax(-clip, fmin(clip, d));
+  out[i] = make_float4((float)x, (float)y, (float)z, (float)t);
+}
+
+// ---------------------------------------------------------------------------
+// Learned distance table of each learned particle over its coupling box:
+// tables[pid * cap + lx + sx (ly + sy lz)] = R_c net(R^T (x - X) / R_c).
+// grid = (ceil(cap / 64), n); one wave evaluates 64 cells as four 16-cell tiles.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_mlp_table(Lattice L, const DevParticle *__restrict__ parts,
+                                                  const float *th_cube, const __bf16 *pk_cube, const float *th_sph,
+                                                  const __bf16 *pk_sph, float *__restrict__ tables, long long cap) {
+  const int pid = blockIdx.y;
+  const DevParticle &p = parts[pid];
+  if (!p.learned) return;
+  const int sx = p.hi[0] - p.lo[0] + 1, sy = p.hi[1] - p.lo[1] + 1, sz = p.hi[2] - p.lo[2] + 1;
+  const int total = sx * sy * sz;
+  const int base = blockIdx.x * 64;
+  if (base >= total) return;
+  const MlpArgs A = mlp_args(p.shape == 1 ? th_cube : th_sph, p.shape == 1 ? pk_cube : pk_sph);
+  const int l = threadIdx.x, g = l >> 4, li = l & 15;
+  const int nn[3] = {L.nx, L.ny, L.nz};
+  const double inv = 1.0 / p.rc;
+  for (int q = 0; q < 4; ++q) {
+    const int idx = base + q * 16 + li;
+    const bool ok = idx < total;
+    float x[3] = {0.f, 0.f, 0.f};
+    if (ok) {
+      const int loc[3] = {idx % sx, (idx / sx) % sy, idx / (sx * sy)};
+      double d[3];
+      for (int k = 0; k < 3; ++k) {
+        int v = p.lo[k] + loc[k];
+        if (!L.bc[k]) { v %= nn[k]; if (v < 0) v += nn[k]; }
+        double dv = (v + 0.5) - p.X[k];
+        if (!L.bc[k]) {
+          const double h = 0.5 * nn[k];
+          if (dv > h) dv -= nn[k];
+          else if (dv < -h) dv += nn[k];
+        }
+        d[k] = dv;
+      }
+      for (int k = 0; k < 3; ++k)
+        x[k] = (float)((p.R[0 * 3 + k] * d[0] + p.R[1 * 3 + k] * d[1] + p.R[2 * 3 + k] * d[2]) * inv);
+    }
+    float z1[16], z2[16], z3[16], y;
+    mlp_forward_tile(A, x[0], x[1], x[2], z1, z2, z3, y);
+    if (ok && g == 0) tables[(size_t)pid * cap + idx] = (float)(y * p.rc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_mlp_table(const Lattice &L, const DevParticle *parts, int n, const float *theta_cube,
+                            const __bf16 *packed_cube, const float *theta_sph, const __bf16 *packed_sph,
+                            float *tables, long long cap, hipStream_t s) {
+  if (n <= 0 || !tables) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_table, dim3((unsigned)((cap + 63) / 64), n), dim3(64), 0, s, L, parts, theta_cube,
+                     packed_cube, theta_sph, packed_sph, tables, cap);
+  return hipGetLastError();
+}
+
+hipError_t mlp_pack(const float *theta, __bf16 *packed, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3(4 * 4096 / 256), dim3(256), 0, s, theta, packed);
+  return hipGetLastError();
+}
+
+hipError_t mlp_eval(const float *theta, const __bf16 *packed, const float *pts, float *out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_eval, dim3((n + 63) / 64), dim3(64), 0, s, theta, packed, pts, out, n);
+  return hipGetLastError();
+}
+
+hipError_t mlp_grad(const float *theta, const __bf16 *packed, const float4 *samples, int n, int nblocks,
+                    float scale, float *partial, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int per = ((n + nblocks - 1) / nblocks + 31) / 32 * 32;
+  const int nb = (n + per - 1) / per;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(64), 0, s, theta, packed, samples, n, per, scale, partial);
+  return hipGetLastError();
+}
+
+int mlp_grad_blocks(int n, int nblocks) {
+  const int per = ((n + nblocks - 1) / nblocks + 31) / 32 * 32;
+  return (n + per - 1) / per;
+}
+
+hipError_t mlp_reduce_adam(float *theta, float *m, float *v, const float *partial, int nblocks, float *grad_out,
+                           int do_step, float lr, int step, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float bc1 = 1.f - powf(b1, (float)step), bc2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, theta, m, v, partial,
+                     nblocks, grad_out, do_step, lr, b1, b2, 1e-8f, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t mlp_samples(int shape, double p0, double p1, uint64_t seed, int n, double box, double band, double clip,
+                       int band_only, float4 *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sdf_samples, dim3((n + 255) / 256), dim3(256), 0, s, shape, p0, p1, seed, n, box, band,
+                     clip, band_only, out);
+  return hipGetLastError();
+}
+
+}  // namespace hlbm

@@ -24,7 +24,11 @@ FIELD_RHO, FIELD_U, FIELD_U_PHYS, FIELD_SOLID = 1, 2, 4, 8
 
 EXPORTED = ["hlbm_workspace_size", "hlbm_init", "hlbm_destroy", "hlbm_set_particles",
             "hlbm_set_fields", "hlbm_step", "hlbm_get_forces", "hlbm_get_fields",
-            "hlbm_num_particles", "hlbm_profile_begin", "hlbm_profile_end", "hlbm_last_error"]
+            "hlbm_num_particles", "hlbm_profile_begin", "hlbm_profile_end", "hlbm_mlp_set_params",
+            "hlbm_mlp_get_params", "hlbm_mlp_eval", "hlbm_mlp_gradient", "hlbm_train_indicator",
+            "hlbm_set_indicator", "hlbm_last_error"]
+MLP_NPARAM = 8641
+INDICATOR_EXACT, INDICATOR_LEARNED = 0, 1
 
 
 class hlbm_config(ctypes.Structure):
@@ -33,7 +37,23 @@ class hlbm_config(ctypes.Structure):
                 ("max_particles", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("eps", ctypes.c_double), ("rho_f", ctypes.c_double),
                 ("gravity", ctypes.c_double * 3), ("fluid_accel", ctypes.c_double * 3),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("learned", ctypes.c_int32),
+                ("learned_samples", ctypes.c_int32), ("learned_max_circumradius", ctypes.c_double)]
+
+
+class hlbm_train_opts(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int32), ("holdout", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("lr_final", ctypes.c_double), ("box", ctypes.c_double), ("band", ctypes.c_double),
+                ("clip", ctypes.c_double), ("gate_rms", ctypes.c_double), ("gate_max", ctypes.c_double),
+                ("ref_circumradius", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class hlbm_train_report(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("rms_err", ctypes.c_double), ("max_err", ctypes.c_double),
+                ("train_ms", ctypes.c_double), ("iterations", ctypes.c_int32),
+                ("accepted", ctypes.c_int32)]
 
 
 # byte layout of struct hlbm_particle
@@ -74,6 +94,13 @@ def lib():
         L.hlbm_profile_begin.argtypes = [vp]
         L.hlbm_profile_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
+        L.hlbm_mlp_set_params.argtypes = [vp, i32, vp]
+        L.hlbm_mlp_get_params.argtypes = [vp, i32, vp]
+        L.hlbm_mlp_eval.argtypes = [vp, i32, i32, vp, vp]
+        L.hlbm_mlp_gradient.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+        L.hlbm_train_indicator.argtypes = [vp, i32, vp, ctypes.POINTER(hlbm_train_opts),
+                                           ctypes.POINTER(hlbm_train_report)]
+        L.hlbm_set_indicator.argtypes = [vp, i32, i32]
         L.hlbm_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name != "hlbm_last_error":
@@ -88,7 +115,8 @@ def _check(rc):
 
 
 def make_config(n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps=0.5, rho_f=1.0,
-                gravity=(0.0, 0.0, 0.0), fluid_accel=(0.0, 0.0, 0.0), stream=None):
+                gravity=(0.0, 0.0, 0.0), fluid_accel=(0.0, 0.0, 0.0), stream=None,
+                learned_max_circumradius=0.0, learned_samples=0):
     c = hlbm_config()
     c.nx, c.ny, c.nz = (int(v) for v in n)
     c.bc = (ctypes.c_int32 * 3)(*[int(b) for b in bc])
@@ -98,6 +126,9 @@ def make_config(n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps
     c.gravity = (ctypes.c_double * 3)(*gravity)
     c.fluid_accel = (ctypes.c_double * 3)(*fluid_accel)
     c.stream = stream
+    c.learned = 1 if learned_max_circumradius > 0 else 0
+    c.learned_samples = int(learned_samples)
+    c.learned_max_circumradius = float(learned_max_circumradius)
     return c
 
 
@@ -115,7 +146,7 @@ class Simulation:
 
     def __init__(self, n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps=0.5,
                  rho_f=1.0, gravity=(0.0, 0.0, 0.0), fluid_accel=(0.0, 0.0, 0.0), device=None,
-                 stream=None):
+                 stream=None, learned_max_circumradius=0.0, learned_samples=0):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -123,7 +154,8 @@ class Simulation:
         self.n = tuple(int(v) for v in n)
         self.N = self.n[0] * self.n[1] * self.n[2]
         self.cfg = make_config(n, bc, tau, precision, max_particles, eps, rho_f, gravity,
-                               fluid_accel, ctypes.c_void_p(self.stream.cuda_stream))
+                               fluid_accel, ctypes.c_void_p(self.stream.cuda_stream),
+                               learned_max_circumradius, learned_samples)
         nbytes = ctypes.c_size_t(0)
         _check(lib().hlbm_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
@@ -196,3 +228,44 @@ class Simulation:
         if mask & 8:
             res["B"] = out[k]
         return res
+
+    # ---- learned indicator ---------------------------------------------
+    def mlp_set_params(self, shape, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.size == MLP_NPARAM
+        _check(lib().hlbm_mlp_set_params(self._ctx, int(shape), th.ctypes.data))
+
+    def mlp_get_params(self, shape):
+        th = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check(lib().hlbm_mlp_get_params(self._ctx, int(shape), th.ctypes.data))
+        return th
+
+    def mlp_eval(self, shape, pts):
+        p = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        out = np.zeros(len(p))
+        _check(lib().hlbm_mlp_eval(self._ctx, int(shape), len(p), p.ctypes.data, out.ctypes.data))
+        return out
+
+    def mlp_gradient(self, shape, pts, target):
+        p = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        t = np.ascontiguousarray(target, dtype=np.float64).reshape(-1)
+        g = np.zeros(MLP_NPARAM)
+        loss = ctypes.c_double(0)
+        _check(lib().hlbm_mlp_gradient(self._ctx, int(shape), len(p), p.ctypes.data, t.ctypes.data,
+                                       g.ctypes.data, ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_indicator(self, shape, param, samples=1_000_000, holdout=100_000, iterations=3000,
+                        batch=8192, lr=3e-3, lr_final=3e-5, box=1.1, band=0.05, clip=0.25,
+                        gate_rms=0.02, gate_max=0.1, ref_circumradius=0.0, seed=4):
+        o = hlbm_train_opts(int(samples), int(holdout), int(iterations), int(batch), float(lr),
+                            float(lr_final), float(box), float(band), float(clip), float(gate_rms),
+                            float(gate_max), float(ref_circumradius), int(seed))
+        r = hlbm_train_report()
+        prm = np.ascontiguousarray(list(param) + [0.0] * (3 - len(param)), dtype=np.float64)
+        _check(lib().hlbm_train_indicator(self._ctx, int(shape), prm.ctypes.data, ctypes.byref(o),
+                                          ctypes.byref(r)))
+        return {name: getattr(r, name) for name, _ in hlbm_train_report._fields_}
+
+    def set_indicator(self, shape, mode):
+        _check(lib().hlbm_set_indicator(self._ctx, int(shape), int(mode)))

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_function():
 def test_particle_record_layout_matches_header():
     # 21 doubles + 2 int32 = 176 bytes, field order as declared
     assert H.HLBM_PARTICLE.itemsize == 176
-    assert ctypes.sizeof(H.hlbm_config) == 4 * 8 + 8 * 9 + 8
+    assert ctypes.sizeof(H.hlbm_config) == 4 * 8 + 8 * 9 + 8 + 4 + 4 + 8
 
 
 def _size(**kw):

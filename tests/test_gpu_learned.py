@@ -1,0 +1,115 @@
+"""Learned indicator on the GPU, through the C ABI: the BF16 matrix-core
+forward pass and gradient against the FP64 oracle network fed the same
+BF16-rounded operands, training on exact signed distances, the acceptance
+gate and its exact fallback, and the learned coupling against the exact one.
+
+Tolerances: forward |y - y_ref| <= 2e-3 max|y_ref| (FP32 accumulation and the
+rare BF16 rounding flip of an activation computed in FP32 instead of FP64);
+gradient L2-relative <= 1e-3 overall and <= 1e-2 per parameter block."""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+from paper_2312_14172_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_14172_amd import hlbm
+    hlbm.lib()
+    return hlbm
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _sim(H, n=(32, 32, 32), bc=(0, 0, 0), precision="fp64", max_particles=4, rmax=10.0,
+         samples=300_000, **kw):
+    return H.Simulation(n, bc, 0.8, precision, max_particles=max_particles,
+                        learned_max_circumradius=rmax, learned_samples=samples, **kw)
+
+
+BLOCKS = [("W1", 0, 192), ("b1", 192, 256), ("W2", 256, 4352), ("b2", 4352, 4416),
+          ("W3", 4416, 8512), ("b3", 8512, 8576), ("W4", 8576, 8640), ("b4", 8640, 8641)]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_forward_matches_oracle(H, seed):
+    _log(f"gpu: mlp forward seed {seed}")
+    sim = _sim(H)
+    theta = W.mlp_init_params(seed)
+    sim.mlp_set_params(W.ROUNDED_CUBE, theta)
+    pts = W.mlp_points(seed + 20, 3000)
+    y = sim.mlp_eval(W.ROUNDED_CUBE, pts)
+    yref, _ = M.forward(theta.astype(np.float64), pts, bf16=True)
+    err = np.abs(y - yref)
+    _log(f"  max err {err.max():.3e} median {np.median(err):.3e} scale {np.abs(yref).max():.3e}")
+    assert err.max() <= 2e-3 * np.abs(yref).max()
+    assert np.median(err) <= 1e-5 * np.abs(yref).max()
+    np.testing.assert_array_equal(sim.mlp_get_params(W.ROUNDED_CUBE), theta)
+    sim.close()
+
+
+@pytest.mark.parametrize("seed,n", [(0, 4096), (1, 1000), (2, 77)])
+def test_gradient_matches_oracle(H, seed, n):
+    """Batch sizes that fill, and do not fill, the 32-sample pairs and the
+    gradient workgroups."""
+    _log(f"gpu: mlp gradient seed {seed} n {n}")
+    sim = _sim(H)
+    theta = W.mlp_init_params(seed + 3)
+    sim.mlp_set_params(W.SPHEROID, theta)
+    pts = W.mlp_points(seed + 30, n)
+    prm = W.equal_volume_params(W.SPHEROID, 1.0)
+    rc = W.circumradius(W.SPHEROID, prm)
+    from oracle import oracle as O
+    t = np.array([O.Oracle.sdf(W.SPHEROID, np.array(prm) / rc, p) for p in pts])
+    g, L = sim.mlp_gradient(W.SPHEROID, pts, t)
+    gref, Lref = M.gradient(theta.astype(np.float64), pts, t, bf16=True)
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    _log(f"  loss {L:.6e} ref {Lref:.6e}  grad rel {rel:.3e}")
+    assert abs(L - Lref) <= 1e-3 * Lref
+    assert rel <= 1e-3
+    for name, a, b in BLOCKS:
+        rb = np.linalg.norm(g[a:b] - gref[a:b]) / max(np.linalg.norm(gref[a:b]), 1e-30)
+        assert rb <= 1e-2, (name, rb)
+    sim.close()
+
+
+def _train(sim, shape, r_eq, iterations, **kw):
+    prm = W.equal_volume_params(shape, r_eq)
+    sim.mlp_set_params(shape, W.mlp_init_params(7 + shape))
+    rep = sim.train_indicator(shape, prm[:2], iterations=iterations, **kw)
+    return prm, rep
+
+
+def test_training_reduces_loss_and_falls_back_to_exact(H):
+    """A gate no network can pass keeps the exact indicator: the coupled run is
+    bitwise the run of a context that never trained."""
+    n, bc = (40, 40, 40), (0, 0, 1)
+    parts = np.array([W.make_particle(W.ROUNDED_CUBE, W.equal_volume_params(W.ROUNDED_CUBE, 5.0),
+                                      (20.3, 19.6, 21.1), quat=W.shoemake_quaternion(
+                                          np.random.default_rng(2)))])
+    sim = _sim(H, n, bc, samples=240_000)
+    _log("gpu: short training, impossible gate")
+    prm, rep = _train(sim, W.ROUNDED_CUBE, 5.0, 400, samples=200_000, holdout=20_000, batch=4096,
+                      gate_rms=1e-9, gate_max=1e-9)
+    _log(f"  {rep}")
+    assert rep["loss_last"] < 0.2 * rep["loss_first"]
+    assert rep["accepted"] == 0
+    sim.set_particles(parts)
+    sim.step(20)
+    F, T, _ = sim.get_forces()
+    ref = _sim(H, n, bc, samples=1000)
+    ref.set_particles(parts)
+    ref.step(20)
+    Fr, Tr, _ = ref.get_forces()
+    np.testing.assert_array_equal(F, Fr)
+    np.testing.assert_array_equal(T, Tr)
+    sim.close()
+    ref.close()
