@@ -32,7 +32,37 @@ METRIC = "coupled HLBM MLUPS + % HBM roofline, FP32/learned vs FP64 at ≤1% for
 HBM_PEAK_GBS = 8000.0
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f32 (f16 storage)"}
-DEFAULT_PRECISION = {"spheres128": "fp32", "sphere32": "fp64", "mixed256": "fp16s"}
+DEFAULT_PRECISION = {"spheres128": "fp32", "sphere32": "fp64", "mixed256": "fp16s",
+                     "mixed256_learned": "fp16s"}
+# surrogate training settings for the learned-indicator workload
+TRAIN = dict(samples=1_000_000, holdout=100_000, iterations=30000, batch=8192, lr=1e-2, lr_final=1e-5,
+             band=0.1, clip=0.25, band_share=0.8, gate_rms=0.05, gate_max=0.5)
+
+
+def make_sim(H, W, wl, precision):
+    """A context for the workload; for the learned workload the two
+    non-spherical families are trained first (outside any timed region)."""
+    import numpy as np
+    learned = bool(getattr(wl, "learned", False))
+    rmax = 0.0
+    if learned:
+        rmax = max(W.circumradius(int(s), p) for s, p in zip(wl.particles["shape"], wl.particles["param"]))
+    sim = H.Simulation(wl.n, wl.bc, wl.tau, precision, max_particles=len(wl.particles),
+                       gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f,
+                       learned_max_circumradius=rmax + 0.01 if learned else 0.0,
+                       learned_samples=1_100_000 if learned else 0)
+    reports = {}
+    if learned:
+        for s in (W.ROUNDED_CUBE, W.SPHEROID):
+            sel = wl.particles["shape"] == s
+            if not np.any(sel):
+                continue
+            prm = wl.particles["param"][np.argmax(sel)]
+            sim.mlp_set_params(s, W.mlp_init_params(7 + s))
+            reports[W.SHAPE_NAMES[s]] = sim.train_indicator(
+                s, prm[:2], ref_circumradius=W.circumradius(s, prm), **TRAIN)
+    sim.set_particles(wl.particles)
+    return sim, reports
 
 
 def kernel_source_hash() -> str:
@@ -66,11 +96,15 @@ def force_error_vs_fp64(H, wl, precision, steps, every):
     """Time-averaged per-particle force of `precision` vs FP64, RMS-relative."""
     import numpy as np
     import torch
+    from paper_2312_14172_amd import workloads as W
     sums = {}
     for prec in (precision, "fp64"):
-        sim = H.Simulation(wl.n, wl.bc, wl.tau, prec, max_particles=len(wl.particles),
-                           gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f)
-        sim.set_particles(wl.particles)
+        if prec == "fp64":   # the FP64 plain form: exact indicator
+            sim = H.Simulation(wl.n, wl.bc, wl.tau, prec, max_particles=len(wl.particles),
+                               gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f)
+            sim.set_particles(wl.particles)
+        else:
+            sim, _ = make_sim(H, W, wl, prec)
         acc = np.zeros((len(wl.particles), 3))
         for _ in range(steps // every):
             sim.step(every)
@@ -148,9 +182,7 @@ def main():
     print(f"[bench] {wl.name}: {wl.n} cells, {len(wl.particles)} particles, {precision}, "
           f"phi={wl.solid_fraction:.3f}", file=sys.stderr, flush=True)
     H.lib()
-    sim = H.Simulation(wl.n, wl.bc, wl.tau, precision, max_particles=len(wl.particles),
-                       gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f)
-    sim.set_particles(wl.particles)
+    sim, train_reports = make_sim(H, W, wl, precision)
     sim.step(args.warmup)
     sim.get_forces()            # synchronises and reports kernel errors
     torch.cuda.synchronize()
@@ -204,6 +236,9 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
     }
     out.update(extra)
+    if train_reports:
+        out["learned_indicator"] = {k: {kk: (float(f"{vv:.4g}") if isinstance(vv, float) else vv)
+                                        for kk, vv in v.items()} for k, v in train_reports.items()}
     print(json.dumps(out), flush=True)
 
 

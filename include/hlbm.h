@@ -189,7 +189,7 @@ int hlbm_profile_end(hlbm_ctx *ctx, double *collide_ms, int64_t *launches);
 #define HLBM_INDICATOR_LEARNED 1
 
 typedef struct hlbm_train_opts {
-    int32_t samples;     /* training samples, half uniform in the box, half within `band` */
+    int32_t samples;     /* training samples: uniform in the box, or within `band` (band_share) */
     int32_t holdout;     /* held-out samples within `band` (judge the gate) */
     int32_t iterations;  /* Adam steps */
     int32_t batch;       /* samples per step */
@@ -198,6 +198,7 @@ typedef struct hlbm_train_opts {
     double box;          /* sampling cube half-width, in circumradii (e.g. 1.1) */
     double band;         /* near-surface band half-width, in circumradii */
     double clip;         /* targets clipped to +-clip circumradii */
+    double band_share;   /* fraction of training samples drawn within `band` (0..1) */
     double gate_rms;     /* accept if held-out RMS error <= gate_rms ... */
     double gate_max;     /* ... and max error <= gate_max (lattice units at ref size) */
     double ref_circumradius; /* particle size (lattice units) at which the gate is judged */

@@ -266,7 +266,7 @@ void orc_equilibrium_field(const ocfg *cfg, const double *rho, const double *u, 
 /* Bare moments (Sec. 3.1): rho = sum f_i, rho u = sum c_i f_i.  u is three planes. */
 void orc_moments(const ocfg *cfg, const double *f, double *rho, double *u) {
     long N = orc_ncells(cfg);
-#pragma omp parallel for schedule(static) if (N >= 200000)
+#pragma omp parallel for schedule(static) if (N >= 4096)
     for (long x = 0; x < N; ++x) {
         double r = 0, j[3] = {0, 0, 0};
         for (int i = 0; i < Q; ++i) {
@@ -309,7 +309,7 @@ void orc_collide_cell(const ocfg *cfg, const double *f, double B, const double *
 
 void orc_collide(const ocfg *cfg, const double *f, const double *B, const double *us, double *fs) {
     long N = orc_ncells(cfg);
-#pragma omp parallel for schedule(static) if (N >= 200000)
+#pragma omp parallel for schedule(static) if (N >= 4096)
     for (long x = 0; x < N; ++x) {
         double uu[3] = {us[x], us[N + x], us[2 * N + x]};
         orc_collide_cell(cfg, f + Q * x, B[x], uu, fs + Q * x);
@@ -323,7 +323,7 @@ void orc_stream(const ocfg *cfg, const double *fs, double *fn) {
     init_tables();
     int nx = cfg->n[0], ny = cfg->n[1], nz = cfg->n[2];
     long N = orc_ncells(cfg);
-#pragma omp parallel for schedule(static) if (N >= 200000)
+#pragma omp parallel for schedule(static) if (N >= 4096)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {

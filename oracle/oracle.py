@@ -184,8 +184,11 @@ class Oracle:
         return P
 
     def _check_parts(self, P):
+        """Every cell the passes visit for a particle (centre within the
+        circumradius + max(eps/2, 1)) must be reached once, with an unambiguous
+        minimum image: that reach must stay below half of a periodic extent."""
         for p in P:
-            R = self.circumradius(int(p["shape"]), p["prm"]) + 0.5 * self.eps + 2.0
+            R = self.circumradius(int(p["shape"]), p["prm"]) + max(0.5 * self.eps, 1.0)
             for k in range(3):
                 if self.bc[k] == 0 and 2 * R >= self.n[k]:
                     raise ValueError("particle reach exceeds half the periodic box")

@@ -633,15 +633,16 @@ int hlbm_train_indicator(hlbm_ctx *ctx, int32_t shape, const double *param, cons
     return fail(HLBM_EINVAL, "samples + holdout must fit the sample capacity %lld", ctx->lay.pool_cap);
   if (o->batch < 32 || o->batch > o->samples || o->iterations < 1)
     return fail(HLBM_EINVAL, "need 32 <= batch <= samples and iterations >= 1");
-  if (!(o->lr > 0 && o->lr_final > 0 && o->box > 0 && o->band > 0 && o->clip >= o->band))
+  if (!(o->lr > 0 && o->lr_final > 0 && o->box > 0 && o->band > 0 && o->clip >= o->band &&
+        o->band_share >= 0 && o->band_share <= 1))
     return fail(HLBM_EINVAL, "bad learning rate / box / band / clip");
   const auto t0 = std::chrono::steady_clock::now();
   const double Rc = circumradius_host(shape, param);
   const double p0 = param[0] / Rc, p1 = param[1] / Rc;
   hipStream_t s = ctx->stream;
   HIP_TRY(hipStreamSynchronize(s));
-  HIP_TRY(mlp_samples(shape, p0, p1, o->seed, o->samples, o->box, o->band, o->clip, 0, ctx->pool, s));
-  HIP_TRY(mlp_samples(shape, p0, p1, o->seed ^ 0x5bd1e995ull, o->holdout, o->box, o->band, o->clip, 1,
+  HIP_TRY(mlp_samples(shape, p0, p1, o->seed, o->samples, o->box, o->band, o->clip, o->band_share, ctx->pool, s));
+  HIP_TRY(mlp_samples(shape, p0, p1, o->seed ^ 0x5bd1e995ull, o->holdout, o->box, o->band, o->clip, 1.0,
                       ctx->pool + o->samples, s));
   HIP_TRY(launch_fill_int((int *)ctx->mom1[f], 0, MLP_PARTIAL, s));
   HIP_TRY(launch_fill_int((int *)ctx->mom2[f], 0, MLP_PARTIAL, s));

@@ -28,6 +28,6 @@ int mlp_grad_blocks(int n, int nblocks);
 hipError_t mlp_reduce_adam(float *theta, float *m, float *v, const float *partial, int nblocks, float *grad_out,
                            int do_step, float lr, int step, hipStream_t s);
 hipError_t mlp_samples(int shape, double p0, double p1, uint64_t seed, int n, double box, double band, double clip,
-                       int band_only, float4 *out, hipStream_t s);
+                       double band_share, float4 *out, hipStream_t s);
 
 }  // namespace hlbm

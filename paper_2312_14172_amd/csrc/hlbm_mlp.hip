@@ -315,8 +315,9 @@ __global__ void k_mlp_reduce_adam(float *__restrict__ theta, float *__restrict__
 // ---------------------------------------------------------------------------
 // Training samples from the exact signed distance (normalised units: the
 // shape is scaled to circumradius 1).  Counter-based random numbers
-// (splitmix64 of seed and sample index).  Even samples are uniform in
-// [-box, box]^3; odd samples are drawn until |d| <= band (at most 64 tries).
+// (splitmix64 of seed and sample index).  Samples are uniform in
+// [-box, box]^3 except a share `band_share` that is redrawn until |d| <= band
+// (at most 64 tries).
 // ---------------------------------------------------------------------------
 __device__ inline uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
@@ -330,10 +331,10 @@ __device__ inline double uniform01(uint64_t seed, uint64_t idx, int k) {
 }
 
 __global__ void k_sdf_samples(int shape, double p0, double p1, uint64_t seed, int n, double box, double band,
-                              double clip, int band_only, float4 *__restrict__ out) {
+                              double clip, double band_share, float4 *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const bool want_band = band_only || (i & 1);
+  const bool want_band = uniform01(seed, i, 1000) < band_share;
   double x = 0, y = 0, z = 0, d = 0;
   for (int k = 0; k < 64; ++k) {
     x = (2.0 * uniform01(seed, i, 3 * k) - 1.0) * box;
@@ -439,10 +440,10 @@ hipError_t mlp_reduce_adam(float *theta, float *m, float *v, const float *partia
 }
 
 hipError_t mlp_samples(int shape, double p0, double p1, uint64_t seed, int n, double box, double band, double clip,
-                       int band_only, float4 *out, hipStream_t s) {
+                       double band_share, float4 *out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sdf_samples, dim3((n + 255) / 256), dim3(256), 0, s, shape, p0, p1, seed, n, box, band,
-                     clip, band_only, out);
+                     clip, band_share, out);
   return hipGetLastError();
 }
 

@@ -45,7 +45,8 @@ class hlbm_train_opts(ctypes.Structure):
     _fields_ = [("samples", ctypes.c_int32), ("holdout", ctypes.c_int32),
                 ("iterations", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
                 ("lr_final", ctypes.c_double), ("box", ctypes.c_double), ("band", ctypes.c_double),
-                ("clip", ctypes.c_double), ("gate_rms", ctypes.c_double), ("gate_max", ctypes.c_double),
+                ("clip", ctypes.c_double), ("band_share", ctypes.c_double),
+                ("gate_rms", ctypes.c_double), ("gate_max", ctypes.c_double),
                 ("ref_circumradius", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
@@ -257,10 +258,10 @@ class Simulation:
 
     def train_indicator(self, shape, param, samples=1_000_000, holdout=100_000, iterations=3000,
                         batch=8192, lr=3e-3, lr_final=3e-5, box=1.1, band=0.05, clip=0.25,
-                        gate_rms=0.02, gate_max=0.1, ref_circumradius=0.0, seed=4):
+                        band_share=0.5, gate_rms=0.02, gate_max=0.1, ref_circumradius=0.0, seed=4):
         o = hlbm_train_opts(int(samples), int(holdout), int(iterations), int(batch), float(lr),
-                            float(lr_final), float(box), float(band), float(clip), float(gate_rms),
-                            float(gate_max), float(ref_circumradius), int(seed))
+                            float(lr_final), float(box), float(band), float(clip), float(band_share),
+                            float(gate_rms), float(gate_max), float(ref_circumradius), int(seed))
         r = hlbm_train_report()
         prm = np.ascontiguousarray(list(param) + [0.0] * (3 - len(param)), dtype=np.float64)
         _check(lib().hlbm_train_indicator(self._ctx, int(shape), prm.ctypes.data, ctypes.byref(o),

@@ -268,7 +268,8 @@ def mixed_shapes(n=256, count=2000, r_eq=6.0, seed=3, tau=0.6, steps=1000, preci
     for k, i in enumerate(order):
         recs.append(make_particle(int(shapes[i]), prms[i], pos[k], quat=quats[i],
                                   density_ratio=density_ratio))
-    w = Workload(f"mixed{n}", (n, n, n), (0, 0, 1), tau, steps, precision, seed=seed,
+    w = Workload(f"mixed{n}" + ("_learned" if learned else ""), (n, n, n), (0, 0, 1), tau, steps,
+                 precision, seed=seed,
                  density_ratio=density_ratio, learned=learned,
                  description=f"{n}^3, z walls, {count} mixed shapes r_eq={r_eq}, tau={tau}")
     w.particles = np.array(recs)

@@ -113,3 +113,58 @@ def test_training_reduces_loss_and_falls_back_to_exact(H):
     np.testing.assert_array_equal(T, Tr)
     sim.close()
     ref.close()
+
+
+TRAIN = dict(samples=1_000_000, holdout=100_000, iterations=30000, batch=8192, lr=1e-2, lr_final=1e-5,
+             band=0.1, clip=0.25, band_share=0.8, gate_rms=0.05, gate_max=0.5)
+
+
+def test_learned_coupling_against_exact(H):
+    """Rounded cubes and spheroids (volume of a sphere of radius 6) with
+    trained networks against the exact indicator on the same workload:
+    porosity on smoothed-boundary cells, solid volume, time-averaged forces
+    (<= 1 % RMS over particles) and the step time with each."""
+    import time
+    import torch
+    n, bc = (96, 96, 96), (0, 0, 1)
+    rng = np.random.default_rng(11)
+    shapes = [W.ROUNDED_CUBE, W.SPHEROID] * 3
+    prms = [W.equal_volume_params(s, 6.0) for s in shapes]
+    rcs = np.array([W.circumradius(s, p) for s, p in zip(shapes, prms)])
+    pos = W.rsa_positions(rng, rcs, n, bc, gap=2.0, wall_margin=2.0)
+    parts = np.array([W.make_particle(s, p, x, quat=W.shoemake_quaternion(rng))
+                      for s, p, x in zip(shapes, prms, pos)])
+    out = {}
+    for mode in ("exact", "learned"):
+        _log(f"gpu: coupled run, {mode} indicator")
+        sim = _sim(H, n, bc, "fp32", max_particles=8, samples=1_100_000, gravity=(0, 0, -1e-5))
+        if mode == "learned":
+            for s in (W.ROUNDED_CUBE, W.SPHEROID):
+                p = W.equal_volume_params(s, 6.0)
+                sim.mlp_set_params(s, W.mlp_init_params(7 + s))
+                rep = sim.train_indicator(s, p[:2], ref_circumradius=W.circumradius(s, p), **TRAIN)
+                _log(f"  family {s}: {rep}")
+                assert rep["accepted"] == 1
+        sim.set_particles(parts)
+        B0 = sim.get_fields(H.FIELD_SOLID)["B"]
+        acc = np.zeros((len(parts), 3))
+        for _ in range(30):
+            sim.step(10)
+            acc += sim.get_forces()[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(200)
+        torch.cuda.synchronize()
+        out[mode] = dict(B0=B0, F=acc / 30, ms=(time.perf_counter() - t0) / 200 * 1e3)
+        sim.close()
+    ex, le = out["exact"], out["learned"]
+    band = ((ex["B0"] > 0) & (ex["B0"] < 1)) | ((le["B0"] > 0) & (le["B0"] < 1))
+    dB = np.abs(le["B0"] - ex["B0"])[band]
+    ferr = np.sqrt(np.mean(np.sum((le["F"] - ex["F"]) ** 2, 1)) / np.mean(np.sum(ex["F"] ** 2, 1)))
+    _log(f"  porosity L1 {dB.mean():.4f} Linf {dB.max():.4f}  volume {le['B0'].sum():.1f} vs "
+         f"{ex['B0'].sum():.1f}  force RMS rel {ferr:.4f}  step ms learned {le['ms']:.4f} "
+         f"exact {ex['ms']:.4f} (learned/exact {le['ms'] / ex['ms']:.2f})")
+    assert ferr <= 0.01
+    assert dB.mean() <= 0.05
+    assert abs(le["B0"].sum() / ex["B0"].sum() - 1) <= 5e-3
+    assert le["ms"] > 0 and ex["ms"] > 0
