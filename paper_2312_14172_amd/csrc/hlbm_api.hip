@@ -56,7 +56,7 @@ int validate(const hlbm_config *c) {
   if (!c) return fail(HLBM_EINVAL, "config is NULL");
   if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(HLBM_EINVAL, "lattice size must be >= 1");
   const long long N = (long long)c->nx * c->ny * c->nz;
-  if (N * 19 >= (1LL << 40)) return fail(HLBM_EINVAL, "lattice too large");
+  if (N >= (1LL << 31)) return fail(HLBM_EINVAL, "lattice too large (at most 2^31 - 1 cells)");
   for (int k = 0; k < 3; ++k)
     if (c->bc[k] != HLBM_BC_PERIODIC && c->bc[k] != HLBM_BC_WALL)
       return fail(HLBM_EINVAL, "bc[%d] must be HLBM_BC_PERIODIC or HLBM_BC_WALL", k);

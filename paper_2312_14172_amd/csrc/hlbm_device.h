@@ -74,47 +74,57 @@ __device__ inline int box_offset(int v, int lo, int n, int periodic) {
 }
 
 // ---------------------------------------------------------------------------
-// Population storage.  All formats hold the deviation g_i = f_i - w_i.
-// G is the precision of the particle geometry in the lattice kernels.
+// Population storage.  Every format holds the relative deviation
+//   s_i = K (f_i - w_i) / w_i
+// (K = 1 for FP64 / FP32, K = 256 for FP16S), so the equilibrium needs no
+// per-direction weight:  K (feq_i - w_i) / w_i = K (rho - 1) + K rho (3 c.u +
+// 4.5 (c.u)^2 - 1.5 u.u),  and FP16 deviations down to ~2e-7 stay normal.
+// T is the arithmetic precision, G the precision of particle geometry.
 // ---------------------------------------------------------------------------
 struct StoreF64 {
   using S = double;
   using T = double;
   using G = double;
   static constexpr int kind = 0;
-  __device__ static inline T dec(S v, int) { return v; }
-  __device__ static inline S enc(T g, int) { return g; }
+  __device__ static constexpr double K() { return 1.0; }
+  __device__ static inline T dec(S v) { return v; }
+  __device__ static inline S enc(T v) { return v; }
 };
 struct StoreF32 {
   using S = float;
   using T = float;
   using G = float;
   static constexpr int kind = 1;
-  __device__ static inline T dec(S v, int) { return v; }
-  __device__ static inline S enc(T g, int) { return g; }
+  __device__ static constexpr float K() { return 1.0f; }
+  __device__ static inline T dec(S v) { return v; }
+  __device__ static inline S enc(T v) { return v; }
 };
-// FP16 holding 256 (f_i - w_i) / w_i: every direction uses the same relative
-// range, and deviations down to ~2e-7 of w_i stay normal numbers.
 struct StoreF16S {
   using S = _Float16;
   using T = float;
   using G = float;
   static constexpr int kind = 2;
-  __device__ static inline T dec(S v, int i) {
-    return (float)v * (i == 0 ? (1.0f / 768.0f) : (i <= 6 ? (1.0f / 4608.0f) : (1.0f / 9216.0f)));
-  }
-  __device__ static inline S enc(T g, int i) {
-    return (_Float16)(g * (i == 0 ? 768.0f : (i <= 6 ? 4608.0f : 9216.0f)));
-  }
+  __device__ static constexpr float K() { return 256.0f; }
+  __device__ static inline T dec(S v) { return (float)v; }
+  __device__ static inline S enc(T v) { return (_Float16)v; }
 };
+
+// Population f_i in FP64 from a stored value.
+template <class ST>
+__device__ inline double pop_f64(typename ST::S v, int i) {
+  return wgt(i) * (1.0 + (double)ST::dec(v) / (double)ST::K());
+}
 
 // ---------------------------------------------------------------------------
 // Geometry.  Signed distances are negative inside (Sec. 3.2).
 // ---------------------------------------------------------------------------
+// Reciprocal: exact division in FP64, the hardware reciprocal (1 ulp) in FP32.
+__device__ inline double frcp(double v) { return 1.0 / v; }
+__device__ inline float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ inline double dsqrt(double v) { return sqrt(v); }
 __device__ inline float dsqrt(float v) { return sqrtf(v); }
 __device__ inline double dcos(double v) { return cos(v); }
-__device__ inline float dcos(float v) { return cosf(v); }
+__device__ inline float dcos(float v) { return __cosf(v); }
 __device__ inline double dabs(double v) { return fabs(v); }
 __device__ inline float dabs(float v) { return fabsf(v); }
 __device__ inline double dmax(double a, double b) { return fmax(a, b); }
@@ -133,14 +143,20 @@ __device__ inline G ellipse_distance(G e0, G e1, G y0, G y1) {
   if (y1 > G(0)) {
     if (y0 > G(0)) {
       const G a = e0 * y0, b = e1 * y1;
-      G t = b - e1s;
+      const G lo = b - e1s;  // G(lo) >= 0
+      // Newton from t = 0 (the root for a point on the surface).  Outside,
+      // G(0) > 0 and the iteration increases monotonically to the root; inside,
+      // the first step overshoots to the left of the root (G is convex), is
+      // clamped to the bracket, and the iteration then increases monotonically.
+      G t = G(0);
       for (int it = 0; it < 100; ++it) {
-        const G p0 = t + e0s, p1 = t + e1s;
-        const G r0 = a / p0, r1 = b / p1;
+        const G i0 = frcp(t + e0s), i1 = frcp(t + e1s);
+        const G r0 = a * i0, r1 = b * i1;
         const G gv = r0 * r0 + r1 * r1 - G(1);
-        const G dg = G(-2) * (r0 * r0 / p0 + r1 * r1 / p1);
-        const G tn = t - gv / dg;
-        if (!(tn > t)) break;
+        const G dg = G(-2) * (r0 * r0 * i0 + r1 * r1 * i1);
+        G tn = t - gv * frcp(dg);
+        if (tn < lo) tn = lo;
+        if (it > 0 && !(tn > t)) break;
         t = tn;
       }
       const G x0 = e0s * y0 / (t + e0s), x1 = e1s * y1 / (t + e1s);
@@ -177,12 +193,13 @@ __device__ inline G sdf_body(int shape, G p0, G p1, G b0, G b1, G b2) {
 
 // Signed distance for the indicator, with a cheap classification of cells that
 // are certainly farther than eps/2 from the surface: returns +-1e30 there.
+// ia2, ib2 = 1/p0^2, 1/p1^2.
 template <typename G>
-__device__ inline G sdf_for_indicator(int shape, G p0, G p1, G b0, G b1, G b2, G half_eps) {
+__device__ inline G sdf_for_indicator(int shape, G p0, G p1, G ia2, G ib2, G b0, G b1, G b2, G half_eps) {
   if (shape == 2) {
     // s^2 = implicit value; |d| >= |s - 1| * min(p0, p1) (the scaled spheroids
     // s E and E are at least that far apart), so only a thin shell iterates.
-    const G k = (b0 * b0) / (p0 * p0) + (b1 * b1 + b2 * b2) / (p1 * p1);
+    const G k = b0 * b0 * ia2 + (b1 * b1 + b2 * b2) * ib2;
     const G s = dsqrt(k);
     if (dabs(s - G(1)) * dmin(p0, p1) >= half_eps) return k <= G(1) ? G(-1e30) : G(1e30);
   }
@@ -205,10 +222,10 @@ __device__ inline bool inside_body(int shape, double p0, double p1, double b0, d
 // Trigonometric indicator B(d) (Sec. 3.2 level-set equation), read as
 // cos^2((pi/2)(d/eps + 1/2)) inside the band |d| < eps/2.
 template <typename G>
-__device__ inline G indicator(G d, G eps) {
+__device__ inline G indicator(G d, G eps, G inv_eps) {
   if (d <= G(-0.5) * eps) return G(1);
   if (d >= G(0.5) * eps) return G(0);
-  const G c = dcos(G(1.5707963267948966) * (d / eps + G(0.5)));
+  const G c = dcos(G(1.5707963267948966) * (d * inv_eps + G(0.5)));
   return c * c;
 }
 

@@ -197,7 +197,7 @@ __device__ inline void pull_all(const Lattice &L, const typename ST::S *__restri
   if constexpr (I < Q) {
     int plane;
     const long long idx = pull_src<I>(L, cp, P, plane);
-    g[I] = ST::dec(A[(long long)plane * L.N + idx], I);
+    g[I] = ST::dec(A[(long long)plane * L.N + idx]);
     pull_all<ST, I + 1>(L, A, cp, P, g);
   }
 }
@@ -295,8 +295,8 @@ __global__ __launch_bounds__(256) void k_mea(Lattice L, const typename ST::S *__
                       (kCY[i] == 1 ? okyp : (kCY[i] == -1 ? okym : true)) &&
                       (kCZ[i] == 1 ? okzp : (kCZ[i] == -1 ? okzm : true));
       const long long nb = ex + (long long)L.nx * (ey + (long long)L.ny * ez);
-      const double fin = (double)ST::dec(A[(long long)i * L.N + cell], i) + wgt(i);
-      const double fout = (double)ST::dec(A[(long long)opp(i) * L.N + nb], opp(i)) + wgt(i);
+      const double fin = pop_f64<ST>(A[(long long)i * L.N + cell], i);
+      const double fout = pop_f64<ST>(A[(long long)opp(i) * L.N + nb], opp(i));
       const double m = ok ? 1.0 : 0.0;
       h[0] += m * ((kCX[i] - upx) * fin + (kCX[i] + upx) * fout);
       h[1] += m * ((kCY[i] - upy) * fin + (kCY[i] + upy) * fout);
@@ -416,7 +416,8 @@ struct Cand {
   G p0, p1;
   G off[3];      // 1/2 - frac(X)
   G reach2;      // (rc + eps/2)^2: B = 0 beyond
-  G inner2;      // sphere: (r - eps/2)^2, B = 1 within
+  G inner2;      // (r_in - eps/2)^2 with r_in the inscribed radius: B = 1 within
+  G ia2, ib2;    // spheroid: 1 / p0^2, 1 / p1^2
   int Xi[3];     // floor(X)
   int lo[3], hi[3];
   int shape;
@@ -461,8 +462,12 @@ __device__ inline void load_candidates(const Lattice &L, const DevParticle *part
     c.p1 = (G)p.prm[1];
     const double ro = p.rc + 0.5 * L.eps;
     c.reach2 = (G)(ro * ro);
-    const double ri = fmax(p.prm[0] - 0.5 * L.eps, 0.0);
-    c.inner2 = (p.shape == 0) ? (G)(ri * ri) : G(-1);
+    // inscribed radius: sphere r, rounded cube h, spheroid min(a, b)
+    const double rin = p.shape == 2 ? fmin(p.prm[0], p.prm[1]) : p.prm[0];
+    const double ri = rin - 0.5 * L.eps;
+    c.inner2 = ri > 0.0 ? (G)(ri * ri) : G(-1);
+    c.ia2 = (G)(1.0 / (p.prm[0] * p.prm[0]));
+    c.ib2 = (G)(1.0 / (p.prm[1] * p.prm[1]));
     c.shape = p.shape;
     c.tab = (p.learned && L.tables) ? (long long)id * L.table_cap : -1;
     c.tsx = p.hi[0] - p.lo[0] + 1;
@@ -491,57 +496,122 @@ __device__ inline G axis_offset(int cell, int xi, G off, int n, int periodic) {
   return d;
 }
 
-// S0 = sum_p B_p and S1 = sum_p B_p u_p(x) over the tile's particles at one
-// cell (Sec. 3.2; overlap reading: B = min(1, S0), u_s = S1 / S0).
+// Per-tile coupling fields in LDS: for every cell of the tile
+//   S0 = sum_p B_p,  S1 = sum_p B_p u_p(x)      (Sec. 3.2; overlap reading:
+//   B = min(1, S0), u_s = S1 / S0).
+// The tile's particles are processed one after the other in index order; for
+// each, the cells of its coupling box inside the tile are spread densely over
+// the workgroup, so only those cells are evaluated and every LDS entry has a
+// single writer per pass (fixed summation order).
 template <typename G>
-__device__ inline void coupling_at(const Lattice &L, const TileCands<G> &tc, const CellPos &cp, G &S0,
-                                   G *S1) {
-  S0 = G(0);
-  S1[0] = S1[1] = S1[2] = G(0);
+struct TileFields {
+  G S0[TZ * TY * TX];
+  G S1[3][TZ * TY * TX];
+};
+
+// Up to two pieces of [lo, hi] (unwrapped) inside the tile range [t0, t0 + ts)
+// of an axis of extent n, as local tile coordinates.
+__device__ inline int axis_pieces(int lo, int hi, int t0, int ts, int n, int periodic, int *a, int *b) {
+  int cnt = 0;
+  const int t1 = min(t0 + ts, n) - 1;
+  for (int k = periodic ? -1 : 0; k <= (periodic ? 1 : 0); ++k) {
+    const int x0 = max(lo, t0 + k * n), x1 = min(hi, t1 + k * n);
+    if (x0 <= x1 && cnt < 2) {
+      a[cnt] = x0 - k * n - t0;
+      b[cnt] = x1 - k * n - t0;
+      ++cnt;
+    }
+  }
+  return cnt;
+}
+
+template <typename G>
+__device__ inline G cell_indicator(const Lattice &L, const Cand<G> &c, int x, int y, int z, G &d0, G &d1, G &d2,
+                                   G he, G eps, G inv_eps) {
+  d0 = axis_offset<G>(x, c.Xi[0], c.off[0], L.nx, !L.bc[0]);
+  d1 = axis_offset<G>(y, c.Xi[1], c.off[1], L.ny, !L.bc[1]);
+  d2 = axis_offset<G>(z, c.Xi[2], c.off[2], L.nz, !L.bc[2]);
+  const G r2 = d0 * d0 + d1 * d1 + d2 * d2;
+  if (!(r2 < c.reach2)) return G(0);
+  if (r2 <= c.inner2) return G(1);  // inside the inscribed sphere shrunk by eps/2
+  if (c.tab >= 0) {
+    const int lx = box_offset(x, c.lo[0], L.nx, !L.bc[0]);
+    const int ly = box_offset(y, c.lo[1], L.ny, !L.bc[1]);
+    const int lz = box_offset(z, c.lo[2], L.nz, !L.bc[2]);
+    return indicator<G>((G)L.tables[c.tab + lx + c.tsx * (ly + c.tsy * lz)], eps, inv_eps);
+  }
+  if (c.shape == 0) return indicator<G>(dsqrt(r2) - c.p0, eps, inv_eps);
+  const G b0 = c.R[0] * d0 + c.R[3] * d1 + c.R[6] * d2;
+  const G b1 = c.R[1] * d0 + c.R[4] * d1 + c.R[7] * d2;
+  const G b2 = c.R[2] * d0 + c.R[5] * d1 + c.R[8] * d2;
+  return indicator<G>(sdf_for_indicator<G>(c.shape, c.p0, c.p1, c.ia2, c.ib2, b0, b1, b2, he), eps, inv_eps);
+}
+
+// Fills tf for tile (tx, ty, tz); ends with a barrier.  Skips everything when
+// the tile has no particles (tf is then not touched).
+template <typename G>
+__device__ inline void tile_coupling(const Lattice &L, const TileCands<G> &tc, int tx, int ty, int tz,
+                                     TileFields<G> &tf) {
+  const int nc = tc.n;
+  if (nc == 0) return;
+  const int ncell = TZ * TY * TX;
+  for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+    tf.S0[k] = G(0);
+    tf.S1[0][k] = tf.S1[1][k] = tf.S1[2][k] = G(0);
+  }
+  __syncthreads();
   const G he = G(0.5) * (G)L.eps;
   const G eps = (G)L.eps;
-  for (int ci = 0; ci < tc.n; ++ci) {
+  const G inv_eps = (G)(1.0 / L.eps);
+  for (int ci = 0; ci < nc; ++ci) {
     const Cand<G> &c = tc.c[ci];
-    // row test, uniform across the wave
-    if (!in_range(cp.y, c.lo[1], c.hi[1], L.ny, !L.bc[1]) || !in_range(cp.z, c.lo[2], c.hi[2], L.nz, !L.bc[2]))
-      continue;
-    const bool lane = cp.act && in_range(cp.x, c.lo[0], c.hi[0], L.nx, !L.bc[0]);
-    if (!lane) continue;
-    const G d0 = axis_offset<G>(cp.x, c.Xi[0], c.off[0], L.nx, !L.bc[0]);
-    const G d1 = axis_offset<G>(cp.y, c.Xi[1], c.off[1], L.ny, !L.bc[1]);
-    const G d2 = axis_offset<G>(cp.z, c.Xi[2], c.off[2], L.nz, !L.bc[2]);
-    const G r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    if (!(r2 < c.reach2)) continue;
-    G Bp;
-    if (c.tab >= 0) {
-      const int lx = box_offset(cp.x, c.lo[0], L.nx, !L.bc[0]);
-      const int ly = box_offset(cp.y, c.lo[1], L.ny, !L.bc[1]);
-      const int lz = box_offset(cp.z, c.lo[2], L.nz, !L.bc[2]);
-      Bp = indicator<G>((G)L.tables[c.tab + lx + c.tsx * (ly + c.tsy * lz)], eps);
-    } else if (c.shape == 0) {
-      Bp = (r2 <= c.inner2) ? G(1) : indicator<G>(dsqrt(r2) - c.p0, eps);
-    } else {
-      const G b0 = c.R[0] * d0 + c.R[3] * d1 + c.R[6] * d2;
-      const G b1 = c.R[1] * d0 + c.R[4] * d1 + c.R[7] * d2;
-      const G b2 = c.R[2] * d0 + c.R[5] * d1 + c.R[8] * d2;
-      Bp = indicator<G>(sdf_for_indicator<G>(c.shape, c.p0, c.p1, b0, b1, b2, he), eps);
-    }
-    if (Bp > G(0)) {
-      S0 += Bp;
-      S1[0] += Bp * (c.U[0] + c.W[1] * d2 - c.W[2] * d1);
-      S1[1] += Bp * (c.U[1] + c.W[2] * d0 - c.W[0] * d2);
-      S1[2] += Bp * (c.U[2] + c.W[0] * d1 - c.W[1] * d0);
-    }
+    int ax[2], bx[2], ay[2], by[2], az[2], bz[2];
+    const int nxp = axis_pieces(c.lo[0], c.hi[0], tx * TX, TX, L.nx, !L.bc[0], ax, bx);
+    const int nyp = axis_pieces(c.lo[1], c.hi[1], ty * TY, TY, L.ny, !L.bc[1], ay, by);
+    const int nzp = axis_pieces(c.lo[2], c.hi[2], tz * TZ, TZ, L.nz, !L.bc[2], az, bz);
+    for (int pz = 0; pz < nzp; ++pz)
+      for (int py = 0; py < nyp; ++py)
+        for (int px = 0; px < nxp; ++px) {
+          const int sx = bx[px] - ax[px] + 1, sy = by[py] - ay[py] + 1, sz = bz[pz] - az[pz] + 1;
+          for (int k = threadIdx.x; k < sx * sy * sz; k += blockDim.x) {
+            const int lx = ax[px] + k % sx, ly = ay[py] + (k / sx) % sy, lz = az[pz] + k / (sx * sy);
+            G d0, d1, d2;
+            const G Bp = cell_indicator<G>(L, c, tx * TX + lx, ty * TY + ly, tz * TZ + lz, d0, d1, d2, he, eps,
+                                           inv_eps);
+            if (Bp > G(0)) {
+              const int idx = lx + TX * (ly + TY * lz);
+              tf.S0[idx] += Bp;
+              tf.S1[0][idx] += Bp * (c.U[0] + c.W[1] * d2 - c.W[2] * d1);
+              tf.S1[1][idx] += Bp * (c.U[1] + c.W[2] * d0 - c.W[0] * d2);
+              tf.S1[2][idx] += Bp * (c.U[2] + c.W[0] * d1 - c.W[1] * d0);
+            }
+          }
+        }
+    __syncthreads();
   }
 }
 
 // Fused collide + stream with the exact-difference source (one workgroup per
-// tile):
-//   rho = 1 + sum g_i,  u = sum c_i g_i / rho                 (Sec. 3.1)
-//   du = B (u_s - u) + (1 - B) a_f                            (Sec. 3.2)
-//   g*_i = (1 - 1/tau)(g_i - geq_i(rho, u)) + geq_i(rho, u + du)
-// i.e. f_i - (f_i - feq_i)/tau + feq_i(u + du) - feq_i(u) written for the
-// stored deviations g = f - w, geq = feq - w.
+// tile).  With stored values s_i = K (f_i - w_i) / w_i:
+//   rho = 1 + sum_i w_i s_i / K,   rho u = sum_i w_i c_i s_i / K      (Sec. 3.1)
+//   du = B (u_s - u) + (1 - B) a_f                                  (Sec. 3.2)
+//   e_i(v) = K (rho - 1) + K rho (3 c_i.v + 4.5 (c_i.v)^2 - 1.5 v.v)
+//   s*_i = (1 - 1/tau)(s_i - e_i(u)) + e_i(u + du)
+// which is f_i - (f_i - feq_i(u))/tau + feq_i(u + du) - feq_i(u) in these
+// units; without a source it is s_i - (s_i - e_i(u))/tau.  Opposite
+// directions share the even part of e_i.
+template <class ST>
+__device__ inline void pull_fast(const typename ST::S *__restrict__ A, long long N, int x, int xm, int xp,
+                                 const int *rowsrc, typename ST::T *s) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int sx = kCX[i] == 1 ? xm : (kCX[i] == -1 ? xp : x);
+    const int r = rowsrc[(kCY[i] + 1) * 3 + (kCZ[i] + 1)];
+    const typename ST::S *plane = A + (long long)i * N;
+    s[i] = ST::dec(plane[(unsigned)(sx + r)]);
+  }
+}
+
 template <class ST>
 __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S *__restrict__ A,
                                                  typename ST::S *__restrict__ Bo,
@@ -552,6 +622,7 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
   using T = typename ST::T;
   using G = typename ST::G;
   __shared__ TileCands<G> tc;
+  __shared__ TileFields<G> tf;
   const int tile = blockIdx.x;
   const int tx = tile % L.ntx;
   const int ty = (tile / L.ntx) % L.nty;
@@ -560,47 +631,74 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
   const int nc = tc.n;
   // the other tile-list buffer is refilled by the next step's binning
   if (threadIdx.x == 0 && tcnt_clear) tcnt_clear[tile] = 0;
+  tile_coupling<G>(L, tc, tx, ty, tz, tf);
 
+  const T K = ST::K();
+  const T invK = (T)1 / K;
   const T omega = (T)L.omega;
+  const T one_m_omega = (T)1 - omega;
   const T afx = (T)L.af[0], afy = (T)L.af[1], afz = (T)L.af[2];
   const bool has_af = (L.af[0] != 0.0) || (L.af[1] != 0.0) || (L.af[2] != 0.0);
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
 
   for (int zz = 0; zz < TZ; ++zz) {
     CellPos cp;
     cp.x = tx * TX + lane_id();
     cp.y = ty * TY + wave_id();
     cp.z = tz * TZ + zz;
-    if (cp.z >= L.nz || cp.y >= L.ny) break;
-    cp.act = cp.x < L.nx;
+    if (cp.z >= nz || cp.y >= ny) break;
+    cp.act = cp.x < nx;
+    const int cell = cp.x + nx * (cp.y + ny * cp.z);
 
-    T g[Q];
-    long long cell = 0;
+    T s[Q];
     if (cp.act) {
-      const PullIdx P = pull_index(L, cp);
-      cell = P.cell;
-      pull_all<ST>(L, A, cp, P, g);
+      // rows wholly away from walls take the direct pull: 32-bit offsets from
+      // per-direction plane bases (the condition is uniform over the wave)
+      const bool edge = L.bc[0] || (L.bc[1] && (cp.y == 0 || cp.y == ny - 1)) ||
+                        (L.bc[2] && (cp.z == 0 || cp.z == nz - 1));
+      if (!edge) {
+        const int ys[3] = {cp.y == ny - 1 ? 0 : cp.y + 1, cp.y, cp.y == 0 ? ny - 1 : cp.y - 1};  // source y for c_y = -1, 0, +1
+        const int zs[3] = {cp.z == nz - 1 ? 0 : cp.z + 1, cp.z, cp.z == 0 ? nz - 1 : cp.z - 1};
+        int rowsrc[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) rowsrc[a * 3 + b] = nx * (ys[a] + ny * zs[b]);
+        const int xm = cp.x == 0 ? nx - 1 : cp.x - 1, xp = cp.x == nx - 1 ? 0 : cp.x + 1;
+        pull_fast<ST>(A, L.N, cp.x, xm, xp, rowsrc, s);
+      } else {
+        const PullIdx P = pull_index(L, cp);
+        pull_all<ST>(L, A, cp, P, s);
+      }
     } else {
 #pragma unroll
-      for (int i = 0; i < Q; ++i) g[i] = (T)0;
+      for (int i = 0; i < Q; ++i) s[i] = (T)0;
     }
+    // moments
     T rho1 = (T)0, jx = (T)0, jy = (T)0, jz = (T)0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      rho1 += g[i];
-      if (kCX[i]) jx += kCX[i] * g[i];
-      if (kCY[i]) jy += kCY[i] * g[i];
-      if (kCZ[i]) jz += kCZ[i] * g[i];
+      const T wk = (T)wgt(i) * invK;
+      rho1 += wk * s[i];
+      if (kCX[i]) jx += (T)kCX[i] * wk * s[i];
+      if (kCY[i]) jy += (T)kCY[i] * wk * s[i];
+      if (kCZ[i]) jz += (T)kCZ[i] * wk * s[i];
     }
     const T rho = (T)1 + rho1;
-    const T inv = (T)1 / rho;
+    const T inv = frcp(rho);
     const T ux = jx * inv, uy = jy * inv, uz = jz * inv;
 
     G S0 = G(0), S1[3] = {G(0), G(0), G(0)};
-    if (nc > 0) coupling_at<G>(L, tc, cp, S0, S1);
+    if (nc > 0) {
+      const int idx = lane_id() + TX * (wave_id() + TY * zz);
+      S0 = tf.S0[idx];
+      S1[0] = tf.S1[0][idx]; S1[1] = tf.S1[1][idx]; S1[2] = tf.S1[2][idx];
+    }
     T du0 = afx, du1 = afy, du2 = afz;
     if (S0 > G(0)) {
       const T Bt = (T)(S0 < G(1) ? S0 : G(1));
-      const T usx = (T)(S1[0] / S0), usy = (T)(S1[1] / S0), usz = (T)(S1[2] / S0);
+      const G is0 = frcp(S0);
+      const T usx = (T)(S1[0] * is0), usy = (T)(S1[1] * is0), usz = (T)(S1[2] * is0);
       du0 = Bt * (usx - ux) + ((T)1 - Bt) * afx;
       du1 = Bt * (usy - uy) + ((T)1 - Bt) * afy;
       du2 = Bt * (usz - uz) + ((T)1 - Bt) * afz;
@@ -609,24 +707,38 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
 
     const T usq = ux * ux + uy * uy + uz * uz;
     if (cp.act && !(rho > (T)0 && usq < (T)0.09)) atomicOr(status, ST_UNSTABLE);
-    const T vx = ux + du0, vy = uy + du1, vz = uz + du2;
-    const T vsq = vx * vx + vy * vy + vz * vz;
-    const T one_m_omega = (T)1 - omega;
+    const T Kr1 = K * rho1, Krho = K * rho;
+    const T o3 = (T)3 * Krho, e45 = (T)4.5 * Krho;  // e_i = base + e45 (c.u)^2 + o3 c.u
+    const T base = Kr1 - (T)1.5 * Krho * usq;
+    // plain BGK, then the exact-difference source e_i(u + du) - e_i(u) where
+    // the cell is coupled
+    T out[Q];
+    out[0] = s[0] - omega * (s[0] - base);
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      const T cu = (T)kCX[i] * ux + (T)kCY[i] * uy + (T)kCZ[i] * uz;
+      const T E = base + e45 * cu * cu, O = o3 * cu;
+      out[i] = s[i] - omega * (s[i] - (E + O));
+      out[i + 1] = s[i + 1] - omega * (s[i + 1] - (E - O));
+    }
+    if (coupled) {
+      const T vx = ux + du0, vy = uy + du1, vz = uz + du2;
+      const T dE0 = (T)-1.5 * Krho * ((vx * vx + vy * vy + vz * vz) - usq);
+      out[0] += dE0;
+#pragma unroll
+      for (int i = 1; i < Q; i += 2) {
+        const T cu = (T)kCX[i] * ux + (T)kCY[i] * uy + (T)kCZ[i] * uz;
+        const T cd = (T)kCX[i] * du0 + (T)kCY[i] * du1 + (T)kCZ[i] * du2;
+        const T dE = dE0 + e45 * cd * (cd + (T)2 * cu), dO = o3 * cd;
+        out[i] += dE + dO;
+        out[i + 1] += dE - dO;
+      }
+    }
     if (cp.act) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const T w = (T)wgt(i);
-        const T cu = (T)kCX[i] * ux + (T)kCY[i] * uy + (T)kCZ[i] * uz;
-        const T geq = w * (rho1 + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * usq));
-        T gs;
-        if (coupled) {
-          const T cv = (T)kCX[i] * vx + (T)kCY[i] * vy + (T)kCZ[i] * vz;
-          const T geq2 = w * (rho1 + rho * ((T)3 * cv + (T)4.5 * cv * cv - (T)1.5 * vsq));
-          gs = one_m_omega * (g[i] - geq) + geq2;
-        } else {
-          gs = g[i] - omega * (g[i] - geq);
-        }
-        Bo[(long long)i * L.N + cell] = ST::enc(gs, i);
+        typename ST::S *plane = Bo + (long long)i * L.N;
+        plane[(unsigned)cell] = ST::enc(out[i]);
       }
     }
   }
@@ -647,17 +759,17 @@ __global__ void k_set_fields(Lattice L, typename ST::S *__restrict__ A, const do
   const double r = rho ? rho[cell] : 1.0;
   const double u0 = u ? u[cell] : 0.0, u1 = u ? u[L.N + cell] : 0.0, u2 = u ? u[2 * L.N + cell] : 0.0;
   const double usq = u0 * u0 + u1 * u1 + u2 * u2;
-  double dev[Q];
+  double dev[Q];  // K (feq_i - w_i) / w_i
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double cu = kCX[i] * u0 + kCY[i] * u1 + kCZ[i] * u2;
-    dev[i] = wgt(i) * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
+    dev[i] = (double)ST::K() * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
   }
 #define HLBM_SET_ONE(I)                                                   \
   {                                                                       \
     int plane;                                                            \
     const long long idx = pull_src<I>(L, cp, P, plane);                   \
-    A[(long long)plane * L.N + idx] = ST::enc((typename ST::T)dev[I], I); \
+    A[(long long)plane * L.N + idx] = ST::enc((typename ST::T)dev[I]);    \
   }
   HLBM_SET_ONE(0) HLBM_SET_ONE(1) HLBM_SET_ONE(2) HLBM_SET_ONE(3) HLBM_SET_ONE(4)
   HLBM_SET_ONE(5) HLBM_SET_ONE(6) HLBM_SET_ONE(7) HLBM_SET_ONE(8) HLBM_SET_ONE(9)
@@ -677,11 +789,13 @@ __global__ __launch_bounds__(256) void k_fields(Lattice L, const typename ST::S 
   using T = typename ST::T;
   using G = typename ST::G;
   __shared__ TileCands<G> tc;
+  __shared__ TileFields<G> tf;
   const int tile = blockIdx.x;
   const int tx = tile % L.ntx;
   const int ty = (tile / L.ntx) % L.nty;
   const int tz = tile / (L.ntx * L.nty);
   load_candidates<G>(L, parts, tcnt, tlist, tile, tc);
+  tile_coupling<G>(L, tc, tx, ty, tz, tf);
   for (int zz = 0; zz < TZ; ++zz) {
     CellPos cp;
     cp.x = tx * TX + lane_id();
@@ -695,11 +809,15 @@ __global__ __launch_bounds__(256) void k_fields(Lattice L, const typename ST::S 
     const long long cell = P.cell;
     pull_all<ST>(L, A, cp, P, g);
     G S0 = G(0), S1[3] = {G(0), G(0), G(0)};
-    if (tc.n > 0) coupling_at<G>(L, tc, cp, S0, S1);
+    if (tc.n > 0) {
+      const int idx = lane_id() + TX * (wave_id() + TY * zz);
+      S0 = tf.S0[idx];
+      S1[0] = tf.S1[0][idx]; S1[1] = tf.S1[1][idx]; S1[2] = tf.S1[2][idx];
+    }
     double rho1 = 0, j[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const double gi = (double)g[i];
+      const double gi = wgt(i) * (double)g[i] / (double)ST::K();  // f_i - w_i
       rho1 += gi;
       j[0] += kCX[i] * gi; j[1] += kCY[i] * gi; j[2] += kCZ[i] * gi;
     }
