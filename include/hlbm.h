@@ -61,9 +61,11 @@ extern "C" {
 #define HLBM_BC_WALL 1 /* resting half-way bounce-back walls at 0 and n */
 
 /* population storage / arithmetic */
-#define HLBM_FP64 0  /* FP64 storage and arithmetic */
-#define HLBM_FP32 1  /* FP32 arithmetic, FP32 storage of f_i - w_i */
-#define HLBM_FP16S 2 /* FP32 arithmetic, FP16 storage of 256 (f_i - w_i) / w_i */
+/* Every format stores the relative deviation K (f_i - w_i) / w_i of each
+ * population from its lattice weight (Sec. 3.1 weights). */
+#define HLBM_FP64 0  /* FP64 storage and arithmetic, K = 1 */
+#define HLBM_FP32 1  /* FP32 arithmetic, FP32 storage, K = 1 */
+#define HLBM_FP16S 2 /* FP32 arithmetic, FP16 storage, K = 256 */
 
 /* particle shapes (body-frame parameters in hlbm_particle.param) */
 #define HLBM_SPHERE 0       /* param[0] = radius */
@@ -130,8 +132,9 @@ int hlbm_destroy(hlbm_ctx *ctx);
  * the particle data of Sec. 4.1 (position, orientation, velocity, angular
  * velocity, shape).  Checks: n <= max_particles; finite values; unit
  * quaternion (|q| within 1e-6 of 1, renormalised); inertia > 0; positive
- * shape parameters; a particle's reach (circumradius + 2) below half of
- * every periodic extent; centres inside the domain on wall axes. */
+ * shape parameters; a particle's reach (circumradius + max(eps/2, sqrt 2) + 1)
+ * below half of every periodic extent; centres inside the domain on wall
+ * axes; circumradius below about 27 cells (the tile binning's limit). */
 int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host);
 
 /* Set the fluid to equilibrium f_i = feq_i(rho, u) (Sec. 3.1) from host

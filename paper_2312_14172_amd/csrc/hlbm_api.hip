@@ -46,7 +46,7 @@ constexpr int LMAX_CAP = 56;
 size_t pop_bytes(int precision) { return precision == HLBM_FP64 ? 8 : (precision == HLBM_FP32 ? 4 : 2); }
 
 struct Layout {
-  size_t fA, fB, parts, stage_parts, tcnt[2], tlist[2], partial, status, stage, total;
+  size_t fA, fB, parts, order, stage_parts, tcnt[2], tlist[2], partial, status, stage, total;
   // learned indicator (cfg.learned)
   size_t theta[2], mom1[2], mom2[2], packed[2], gpart, gout, pool, epts, eout, tables;
   long long pool_cap, table_cap;
@@ -101,6 +101,7 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
   y.fA = off; off += pop;
   y.fB = off; off += pop;
   y.parts = off; off += align_up(np * sizeof(DevParticle));
+  y.order = off; off += align_up(np * sizeof(int));
   y.stage_parts = off; off += align_up(np * sizeof(hlbm_particle));
   for (int b = 0; b < 2; ++b) {
     y.tcnt[b] = off; off += align_up((size_t)L.ntiles * sizeof(int));
@@ -142,6 +143,7 @@ struct hlbm_ctx {
   char *base;
   void *fA, *fB;
   DevParticle *parts;
+  int *order;         // particles in (z, y, x) order of their initial centres
   hlbm_particle *stage_parts;
   int *tcnt[2], *tlist[2], *status;
   int cur;            // tile-list buffer describing the current particles
@@ -248,6 +250,7 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   c->fA = c->base + lay.fA;
   c->fB = c->base + lay.fB;
   c->parts = (DevParticle *)(c->base + lay.parts);
+  c->order = (int *)(c->base + lay.order);
   c->stage_parts = (hlbm_particle *)(c->base + lay.stage_parts);
   for (int b = 0; b < 2; ++b) {
     c->tcnt[b] = (int *)(c->base + lay.tcnt[b]);
@@ -398,8 +401,21 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
   }
   if (lmax > LMAX_CAP) return fail(HLBM_EUNSUPPORTED, "circumradius too large");
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  // momentum-exchange workgroups visit the particles in (z, y, x) order of
+  // their centres, so that the workgroups resident at one time read nearby
+  // parts of each population plane (any order gives the same result)
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [host](int a, int b) {
+    const double *pa = host[a].pos, *pb = host[b].pos;
+    if (floor(pa[2]) != floor(pb[2])) return pa[2] < pb[2];
+    if (floor(pa[1]) != floor(pb[1])) return pa[1] < pb[1];
+    if (pa[0] != pb[0]) return pa[0] < pb[0];
+    return a < b;
+  });
   if (n > 0) {
     HIP_TRY(hipMemcpyAsync(ctx->stage_parts, host, sizeof(hlbm_particle) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(launch_prepare(ctx->L, ctx->stage_parts, ctx->parts, n, ctx->stream));
   }
   ctx->n = n;
@@ -441,9 +457,9 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
     if (ctx->n > 0) {
       // momentum exchange on the state of time t, then Newton-Euler -> t+1 and
       // binning of the updated particles into the other tile-list buffer
-      HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->n, ctx->lmax, ctx->partial, s));
-      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, ctx->partial, ctx->tcnt[nxt],
-                             ctx->tlist[nxt], ctx->status, s));
+      HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, ctx->partial, s));
+      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, ctx->partial, ctx->tcnt[nxt], ctx->tlist[nxt],
+                             ctx->status, s));
       int rc = refresh_tables(ctx);
       if (rc) return rc;
     }

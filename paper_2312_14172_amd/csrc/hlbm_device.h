@@ -28,6 +28,21 @@ constexpr int TZ = 4;
 constexpr int MAXC = 48;        // particles a tile can list
 constexpr int MAX_AXIS_TILES = 16;
 
+__device__ inline int wave_id() { return threadIdx.x >> 6; }
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+
+// Sums and minima over the 64 lanes of a wavefront (fixed butterfly order).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 // Status bits raised by kernels.
 constexpr int ST_UNSTABLE = 1;
 constexpr int ST_WALL_EXIT = 2;
@@ -61,6 +76,25 @@ struct DevParticle {
   int lo[3], hi[3];  // cells that can have B > 0 (centre within rc + eps/2), unwrapped
   int learned;       // 1: d_s comes from the particle's learned distance table
 };
+
+// Tiles touched by a cell range along one axis (wrapped on periodic axes),
+// in increasing cell order; returns the count (<= MAX_AXIS_TILES).
+__device__ inline int axis_tiles(int lo, int hi, int n, int periodic, int tsize, int *out) {
+  int cnt = 0, last = -1;
+  for (int c = lo; c <= hi; ++c) {
+    int w = c;
+    if (periodic) { w %= n; if (w < 0) w += n; }
+    if (w < 0 || w >= n) continue;
+    const int t = w / tsize;
+    if (t != last) {
+      bool seen = false;
+      for (int k = 0; k < cnt; ++k) seen |= (out[k] == t);
+      if (!seen && cnt < MAX_AXIS_TILES) out[cnt++] = t;
+      last = t;
+    }
+  }
+  return cnt;
+}
 
 // Offset of a cell inside a particle's coupling box (wrapped on periodic axes);
 // the table index is lx + sx (ly + sy lz).

@@ -1,150 +1,20 @@
-// hlbm_kernels.hip -- gfx950 kernels of the HLBM time step.
+// hlbm_lattice.hip -- gfx950 lattice kernels of the HLBM time step.
 //
 // Storage: populations as structure of arrays A[i][cell] (x fastest), two
 // buffers, pull streaming: the cell x at step t reads f_i(x, t) from
 // A[i][x - c_i] (or A[opp i][x] when x - c_i lies past a wall: half-way
 // bounce-back) and writes its post-collision f*_i(x, t) to B[i][x].
 //
-// One time step (the order of the paper's time-step algorithm, Sec. 4.2):
-//   k_mea_eom   one workgroup per particle: momentum exchange over the cells
-//               of its bounding box (pull form on the stored state), FP64
-//               wavefront-shuffle reduction, gravity and buoyancy, Newton-Euler
-//               and quaternion update in FP64;
-//   k_bin       the particles' coupling boxes -> per-tile particle lists
-//               (tiles of 64 x 4 x 4 cells);
-//   k_collide   one workgroup per tile: the tile's particles staged in LDS,
-//               indicator and solid velocity evaluated at each cell,
-//               exact-difference source, BGK, pull streaming.
+//   k_collide   one workgroup per tile of 64 x 4 x 4 cells: the tile's
+//               particles staged in LDS, the indicator and solid velocity of
+//               the tile's cells accumulated in LDS by a dense pre-pass over
+//               each particle's part of the tile, then per cell: pull,
+//               moments, exact-difference source, BGK, store;
+//   k_set_fields / k_fields   equilibrium initialisation and observables.
 #include "hlbm_device.h"
 #include "hlbm_internal.h"
 
 namespace hlbm {
-
-__device__ inline int wave_id() { return threadIdx.x >> 6; }
-__device__ inline int lane_id() { return threadIdx.x & 63; }
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// ---------------------------------------------------------------------------
-// Particle geometry on the device
-// ---------------------------------------------------------------------------
-__device__ inline void quat_rot(const double *q, double *R) {
-  const double w = q[0], x = q[1], y = q[2], z = q[3];
-  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
-  R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
-  R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
-}
-
-__device__ inline double circumradius(int shape, double p0, double p1) {
-  if (shape == 0) return p0;
-  if (shape == 1) return 1.7320508075688772 * (p0 - p1) + p1;
-  return fmax(p0, p1);
-}
-
-// Cells whose centre lies within `reach` of X along each axis, clipped on
-// wall axes (unwrapped coordinates on periodic axes).
-__device__ inline void cell_box(const Lattice &L, const double *X, double reach, int *lo, int *hi) {
-  const int n[3] = {L.nx, L.ny, L.nz};
-  for (int k = 0; k < 3; ++k) {
-    int a = (int)ceil(X[k] - reach - 0.5);
-    int b = (int)floor(X[k] + reach - 0.5);
-    if (L.bc[k]) {
-      a = max(a, 0);
-      b = min(b, n[k] - 1);
-    }
-    lo[k] = a;
-    hi[k] = b;
-  }
-}
-
-__device__ inline void derive(const Lattice &L, DevParticle &p) {
-  quat_rot(p.q, p.R);
-  p.rc = circumradius(p.shape, p.prm[0], p.prm[1]);
-  cell_box(L, p.X, p.rc + 0.5 * L.eps + 1e-9, p.lo, p.hi);
-}
-
-// Tiles touched by a cell range along one axis (wrapped on periodic axes),
-// in increasing cell order; returns the count (<= MAX_AXIS_TILES).
-__device__ inline int axis_tiles(int lo, int hi, int n, int periodic, int tsize, int *out) {
-  int cnt = 0, last = -1;
-  for (int c = lo; c <= hi; ++c) {
-    int w = c;
-    if (periodic) { w %= n; if (w < 0) w += n; }
-    if (w < 0 || w >= n) continue;
-    const int t = w / tsize;
-    if (t != last) {
-      bool seen = false;
-      for (int k = 0; k < cnt; ++k) seen |= (out[k] == t);
-      if (!seen && cnt < MAX_AXIS_TILES) out[cnt++] = t;
-      last = t;
-    }
-  }
-  return cnt;
-}
-
-__global__ void k_prepare(Lattice L, const hlbm_particle *in, DevParticle *out, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const hlbm_particle s = in[i];
-  DevParticle p;
-  for (int k = 0; k < 3; ++k) {
-    p.X[k] = s.pos[k]; p.U[k] = s.vel[k]; p.W[k] = s.omega[k];
-    p.I[k] = s.inertia[k]; p.prm[k] = s.param[k];
-    p.Fh[k] = 0.0; p.Th[k] = 0.0;
-  }
-  const double nq = sqrt(s.quat[0] * s.quat[0] + s.quat[1] * s.quat[1] + s.quat[2] * s.quat[2] +
-                         s.quat[3] * s.quat[3]);
-  for (int k = 0; k < 4; ++k) p.q[k] = s.quat[k] / nq;
-  p.m = s.mass;
-  p.V = s.volume;
-  p.shape = s.shape;
-  p.flags = s.flags;
-  p.learned = 0;
-  derive(L, p);
-  out[i] = p;
-}
-
-// Mark the particles whose shape family uses its learned indicator (and whose
-// aspect matches the trained one).
-__global__ void k_mark_learned(DevParticle *parts, int n, int mode_cube, double aspect_cube, int mode_sph,
-                               double aspect_sph) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  DevParticle &p = parts[i];
-  const double asp = p.prm[1] / p.prm[0];
-  int on = 0;
-  if (p.shape == 1 && mode_cube) on = fabs(asp - aspect_cube) <= 1e-6 * aspect_cube;
-  if (p.shape == 2 && mode_sph) on = fabs(asp - aspect_sph) <= 1e-6 * aspect_sph;
-  p.learned = on;
-}
-
-__global__ void k_fill_int(int *p, int v, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-// One thread per (particle, tile of its coupling box): append the particle to
-// the tile's list.  grid = (ceil(cap / 64), n).
-__global__ void k_bin(Lattice L, const DevParticle *parts, int *tcnt, int *tlist, int *status) {
-  const int pid = blockIdx.y;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const DevParticle &p = parts[pid];
-  int tx[MAX_AXIS_TILES], ty[MAX_AXIS_TILES], tz[MAX_AXIS_TILES];
-  const int cx = axis_tiles(p.lo[0], p.hi[0], L.nx, !L.bc[0], TX, tx);
-  const int cy = axis_tiles(p.lo[1], p.hi[1], L.ny, !L.bc[1], TY, ty);
-  const int cz = axis_tiles(p.lo[2], p.hi[2], L.nz, !L.bc[2], TZ, tz);
-  if (k >= cx * cy * cz) return;
-  const int a = k % cx, b = (k / cx) % cy, c = k / (cx * cy);
-  const int t = tx[a] + L.ntx * (ty[b] + L.nty * tz[c]);
-  const int slot = atomicAdd(&tcnt[t], 1);
-  if (slot < MAXC) tlist[t * MAXC + slot] = pid;
-  else atomicOr(status, ST_TILE_OVERFLOW);
-}
-
 // ---------------------------------------------------------------------------
 // Pull-index helpers
 // ---------------------------------------------------------------------------
@@ -203,209 +73,19 @@ __device__ inline void pull_all(const Lattice &L, const typename ST::S *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Fluid -> particle (momentum exchange) and equations of motion
-// ---------------------------------------------------------------------------
-__device__ inline void cross_sub(const double *a, const double *b, double *o) {
-  o[0] -= a[1] * b[2] - a[2] * b[1];
-  o[1] -= a[2] * b[0] - a[0] * b[2];
-  o[2] -= a[0] * b[1] - a[1] * b[0];
-}
-
-// Momentum exchange (Sec. 3.2 MEA, force and torque equations) over the cells
-// x_b whose centre is inside the particle, from the stored state of time t in
-// pull storage:
-//   f_i(x_b + c_i, t) = A[i][x_b],  f_opp(i)(x_b, t) = A[opp i][x_b + c_i],
-//   F_h(x_b) = sum_i (c_i - u_p(x_b)) f_i(x_b + c_i) + (c_i + u_p(x_b)) f_opp(i)(x_b)
-// (directions whose neighbour lies past a wall are skipped).  The force on the
-// particle is -sum F_h, the torque -sum (x_b - X) x F_h.
-// One workgroup per (particle, z-layer of its bounding box); each writes the
-// layer's sum, reduced with a fixed wavefront-shuffle tree in FP64.
-template <class ST>
-__global__ __launch_bounds__(256) void k_mea(Lattice L, const typename ST::S *__restrict__ A,
-                                             const DevParticle *__restrict__ parts, int lmax,
-                                             double *__restrict__ partial) {
-  __shared__ double red[4][6];
-  const int pid = blockIdx.x;
-  const int layer = blockIdx.y;
-  const DevParticle &sp = parts[pid];
-  int lo[3], hi[3];
-  cell_box(L, sp.X, sp.rc + 1e-9, lo, hi);
-  if (lo[2] + layer > hi[2]) return;   // uniform per workgroup
-  const int shape = sp.shape;
-  const double p0 = sp.prm[0], p1 = sp.prm[1];
-  const double X[3] = {sp.X[0], sp.X[1], sp.X[2]};
-  const double U[3] = {sp.U[0], sp.U[1], sp.U[2]};
-  const double W[3] = {sp.W[0], sp.W[1], sp.W[2]};
-  double R[9];
-  for (int k = 0; k < 9; ++k) R[k] = sp.R[k];
-  const int sx = hi[0] - lo[0] + 1, sy = hi[1] - lo[1] + 1;
-  const int learned = sp.learned && L.tables;
-  const int tsx = sp.hi[0] - sp.lo[0] + 1, tsy = sp.hi[1] - sp.lo[1] + 1;
-  const int nn[3] = {L.nx, L.ny, L.nz};
-  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  for (int idx = threadIdx.x; idx < sx * sy; idx += blockDim.x) {
-    const int g[3] = {lo[0] + idx % sx, lo[1] + idx / sx, lo[2] + layer};
-    int c[3];
-    double d[3];
-    for (int k = 0; k < 3; ++k) {
-      int v = g[k];
-      if (!L.bc[k]) { v %= nn[k]; if (v < 0) v += nn[k]; }
-      c[k] = v;
-      double dv = (v + 0.5) - X[k];
-      if (!L.bc[k]) {
-        const double h = 0.5 * nn[k];
-        if (dv > h) dv -= nn[k];
-        else if (dv < -h) dv += nn[k];
-      }
-      d[k] = dv;
-    }
-    bool in;
-    if (learned) {
-      const int lx = box_offset(c[0], sp.lo[0], L.nx, !L.bc[0]);
-      const int ly = box_offset(c[1], sp.lo[1], L.ny, !L.bc[1]);
-      const int lz = box_offset(c[2], sp.lo[2], L.nz, !L.bc[2]);
-      in = L.tables[(size_t)pid * L.table_cap + lx + tsx * (ly + tsy * lz)] <= 0.0f;
-    } else {
-      double b[3] = {d[0], d[1], d[2]};
-      if (shape != 0) {
-        b[0] = R[0] * d[0] + R[3] * d[1] + R[6] * d[2];
-        b[1] = R[1] * d[0] + R[4] * d[1] + R[7] * d[2];
-        b[2] = R[2] * d[0] + R[5] * d[1] + R[8] * d[2];
-      }
-      in = inside_body(shape, p0, p1, b[0], b[1], b[2]);
-    }
-    if (!in) continue;
-    const double upx = U[0] + W[1] * d[2] - W[2] * d[1];
-    const double upy = U[1] + W[2] * d[0] - W[0] * d[2];
-    const double upz = U[2] + W[0] * d[1] - W[1] * d[0];
-    const long long cell = c[0] + (long long)L.nx * (c[1] + (long long)L.ny * c[2]);
-    const int xm = c[0] == 0 ? L.nx - 1 : c[0] - 1, xp = c[0] == L.nx - 1 ? 0 : c[0] + 1;
-    const int ym = c[1] == 0 ? L.ny - 1 : c[1] - 1, yp = c[1] == L.ny - 1 ? 0 : c[1] + 1;
-    const int zm = c[2] == 0 ? L.nz - 1 : c[2] - 1, zp = c[2] == L.nz - 1 ? 0 : c[2] + 1;
-    const bool okxm = !(L.bc[0] && c[0] == 0), okxp = !(L.bc[0] && c[0] == L.nx - 1);
-    const bool okym = !(L.bc[1] && c[1] == 0), okyp = !(L.bc[1] && c[1] == L.ny - 1);
-    const bool okzm = !(L.bc[2] && c[2] == 0), okzp = !(L.bc[2] && c[2] == L.nz - 1);
-    double h[3] = {0, 0, 0};
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int ex = kCX[i] == 1 ? xp : (kCX[i] == -1 ? xm : c[0]);
-      const int ey = kCY[i] == 1 ? yp : (kCY[i] == -1 ? ym : c[1]);
-      const int ez = kCZ[i] == 1 ? zp : (kCZ[i] == -1 ? zm : c[2]);
-      const bool ok = (kCX[i] == 1 ? okxp : (kCX[i] == -1 ? okxm : true)) &&
-                      (kCY[i] == 1 ? okyp : (kCY[i] == -1 ? okym : true)) &&
-                      (kCZ[i] == 1 ? okzp : (kCZ[i] == -1 ? okzm : true));
-      const long long nb = ex + (long long)L.nx * (ey + (long long)L.ny * ez);
-      const double fin = pop_f64<ST>(A[(long long)i * L.N + cell], i);
-      const double fout = pop_f64<ST>(A[(long long)opp(i) * L.N + nb], opp(i));
-      const double m = ok ? 1.0 : 0.0;
-      h[0] += m * ((kCX[i] - upx) * fin + (kCX[i] + upx) * fout);
-      h[1] += m * ((kCY[i] - upy) * fin + (kCY[i] + upy) * fout);
-      h[2] += m * ((kCZ[i] - upz) * fin + (kCZ[i] + upz) * fout);
-    }
-    F[0] -= h[0]; F[1] -= h[1]; F[2] -= h[2];
-    cross_sub(d, h, T);
-  }
-  double v[6] = {F[0], F[1], F[2], T[0], T[1], T[2]};
-#pragma unroll
-  for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
-  if (lane_id() == 0) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) red[wave_id()][k] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x < 6) {
-    const int k = threadIdx.x;
-    partial[((size_t)pid * lmax + layer) * 6 + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-  }
-}
-
-// One 64-thread workgroup per particle: sum the layer records in order, add
-// gravity and buoyancy, advance the equations of motion in FP64 with dt = 1
-// (Sec. 2.2; Sec. 5.1 for the external force):
-//   U <- U + (F + (m - rho_f V) g) / m;  X <- X + U (wrapped on periodic axes);
-//   w_b <- w_b + I^-1 (T_b - w_b x I w_b) in the body frame;
-//   q <- normalize(q (x) exp(w_b / 2));  w <- R(q) w_b;
-// then append the particle to the tile lists of its new coupling box.
-__global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restrict__ parts, int lmax,
-                                                const double *__restrict__ partial, int *tcnt, int *tlist,
-                                                int *status) {
-  __shared__ int ts[3][MAX_AXIS_TILES];
-  __shared__ int tn[3];
-  const int pid = blockIdx.x;
-  if (threadIdx.x == 0) {
-    DevParticle p = parts[pid];
-    const int nn[3] = {L.nx, L.ny, L.nz};
-    int lo[3], hi[3];
-    cell_box(L, p.X, p.rc + 1e-9, lo, hi);
-    double Fs[6] = {0, 0, 0, 0, 0, 0};
-    for (int l = 0; l <= hi[2] - lo[2]; ++l)
-      for (int k = 0; k < 6; ++k) Fs[k] += partial[((size_t)pid * lmax + l) * 6 + k];
-    for (int k = 0; k < 3; ++k) { p.Fh[k] = Fs[k]; p.Th[k] = Fs[3 + k]; }
-    if (p.m > 0.0) {
-      const double buoy = p.m - L.rho_f * p.V;
-      for (int k = 0; k < 3; ++k) {
-        p.U[k] += (Fs[k] + buoy * L.g[k]) / p.m;
-        p.X[k] += p.U[k];
-        if (!L.bc[k]) {
-          if (p.X[k] >= nn[k]) p.X[k] -= nn[k];
-          else if (p.X[k] < 0.0) p.X[k] += nn[k];
-        } else if (!(p.X[k] >= 0.0 && p.X[k] <= nn[k])) {
-          atomicOr(status, ST_WALL_EXIT);
-        }
-      }
-      const double *R = p.R;
-      double wb[3], tb[3];
-      for (int k = 0; k < 3; ++k) {
-        wb[k] = R[0 * 3 + k] * p.W[0] + R[1 * 3 + k] * p.W[1] + R[2 * 3 + k] * p.W[2];
-        tb[k] = R[0 * 3 + k] * Fs[3] + R[1 * 3 + k] * Fs[4] + R[2 * 3 + k] * Fs[5];
-      }
-      const double Iw0 = p.I[0] * wb[0], Iw1 = p.I[1] * wb[1], Iw2 = p.I[2] * wb[2];
-      const double g0 = wb[1] * Iw2 - wb[2] * Iw1;
-      const double g1 = wb[2] * Iw0 - wb[0] * Iw2;
-      const double g2 = wb[0] * Iw1 - wb[1] * Iw0;
-      wb[0] += (tb[0] - g0) / p.I[0];
-      wb[1] += (tb[1] - g1) / p.I[1];
-      wb[2] += (tb[2] - g2) / p.I[2];
-      const double ang = sqrt(wb[0] * wb[0] + wb[1] * wb[1] + wb[2] * wb[2]);
-      double d0 = 1.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-      if (ang > 0.0) {
-        double sn, cs;
-        sincos(0.5 * ang, &sn, &cs);
-        const double f = sn / ang;
-        d0 = cs; d1 = f * wb[0]; d2 = f * wb[1]; d3 = f * wb[2];
-      }
-      const double *q = p.q;
-      const double qn[4] = {q[0] * d0 - q[1] * d1 - q[2] * d2 - q[3] * d3,
-                            q[0] * d1 + q[1] * d0 + q[2] * d3 - q[3] * d2,
-                            q[0] * d2 - q[1] * d3 + q[2] * d0 + q[3] * d1,
-                            q[0] * d3 + q[1] * d2 - q[2] * d1 + q[3] * d0};
-      const double nq = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
-      for (int k = 0; k < 4; ++k) p.q[k] = qn[k] / nq;
-      quat_rot(p.q, p.R);
-      for (int k = 0; k < 3; ++k)
-        p.W[k] = p.R[k * 3 + 0] * wb[0] + p.R[k * 3 + 1] * wb[1] + p.R[k * 3 + 2] * wb[2];
-      if (!(p.X[0] == p.X[0] && p.X[1] == p.X[1] && p.X[2] == p.X[2])) atomicOr(status, ST_UNSTABLE);
-      cell_box(L, p.X, p.rc + 0.5 * L.eps + 1e-9, p.lo, p.hi);
-    }
-    parts[pid] = p;
-    tn[0] = axis_tiles(p.lo[0], p.hi[0], L.nx, !L.bc[0], TX, ts[0]);
-    tn[1] = axis_tiles(p.lo[1], p.hi[1], L.ny, !L.bc[1], TY, ts[1]);
-    tn[2] = axis_tiles(p.lo[2], p.hi[2], L.nz, !L.bc[2], TZ, ts[2]);
-  }
-  __syncthreads();
-  const int cx = tn[0], cy = tn[1], cz = tn[2];
-  for (int k = threadIdx.x; k < cx * cy * cz; k += blockDim.x) {
-    const int a = k % cx, b = (k / cx) % cy, c = k / (cx * cy);
-    const int t = ts[0][a] + L.ntx * (ts[1][b] + L.nty * ts[2][c]);
-    const int slot = atomicAdd(&tcnt[t], 1);
-    if (slot < MAXC) tlist[t * MAXC + slot] = pid;
-    else atomicOr(status, ST_TILE_OVERFLOW);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Particle -> fluid coupling evaluated inside the lattice kernels
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin.
+// Workgroup b is given tile (b mod 8) * (ntiles / 8) + b / 8, so that each XCD
+// sweeps one contiguous run of tiles in order and the halo rows that
+// neighbouring tiles share are read through the same L2.  The last
+// ntiles mod 8 tiles map to themselves.
+__device__ inline int xcd_tile(int b, int ntiles) {
+  const int per = ntiles >> 3;
+  if (b >= per * 8) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
 // A tile's particle, staged in LDS, in the geometry precision G.  Offsets are
 // formed as (cell - floor(X)) + (1/2 - frac(X)) so that FP32 keeps the
 // fraction exact to its own rounding.
@@ -623,7 +303,7 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
   using G = typename ST::G;
   __shared__ TileCands<G> tc;
   __shared__ TileFields<G> tf;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(blockIdx.x, L.ntiles);
   const int tx = tile % L.ntx;
   const int ty = (tile / L.ntx) % L.nty;
   const int tz = tile / (L.ntx * L.nty);
@@ -790,7 +470,7 @@ __global__ __launch_bounds__(256) void k_fields(Lattice L, const typename ST::S 
   using G = typename ST::G;
   __shared__ TileCands<G> tc;
   __shared__ TileFields<G> tf;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(blockIdx.x, L.ntiles);
   const int tx = tile % L.ntx;
   const int ty = (tile / L.ntx) % L.nty;
   const int tz = tile / (L.ntx * L.nty);
@@ -850,48 +530,6 @@ static inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b)
     case 1: { using ST = StoreF32; CALL; } break;       \
     default: { using ST = StoreF16S; CALL; } break;     \
   }
-
-hipError_t launch_prepare(const Lattice &L, const hlbm_particle *in, DevParticle *out, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prepare, dim3(blocks_for(n, 128)), dim3(128), 0, s, L, in, out, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_mark_learned(DevParticle *parts, int n, int mode_cube, double aspect_cube, int mode_sph,
-                               double aspect_sph, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mark_learned, dim3(blocks_for(n, 128)), dim3(128), 0, s, parts, n, mode_cube, aspect_cube,
-                     mode_sph, aspect_sph);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_int(int *p, int v, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int cap, int *tcnt, int *tlist,
-                      int *status, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin, dim3(blocks_for(cap, 64), n), dim3(64), 0, s, L, parts, tcnt, tlist, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevParticle *parts, int n, int lmax,
-                      double *partial, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  HLBM_DISPATCH(prec, hipLaunchKernelGGL(k_mea<ST>, dim3(n, lmax), dim3(256), 0, s, L,
-                                         (const typename ST::S *)A, parts, lmax, partial));
-  return hipGetLastError();
-}
-
-hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, const double *partial,
-                          int *tcnt, int *tlist, int *status, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eom_bin, dim3(n), dim3(64), 0, s, L, parts, lmax, partial, tcnt, tlist, status);
-  return hipGetLastError();
-}
 
 hipError_t launch_collide(int prec, const Lattice &L, const void *A, void *B, const DevParticle *parts,
                           const int *tcnt, const int *tlist, int *tcnt_clear, int *status, hipStream_t s) {

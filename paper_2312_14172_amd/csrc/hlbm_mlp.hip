@@ -348,48 +348,80 @@ __global__ void k_sdf_samples(int shape, double p0, double p1, uint64_t seed, in
 }
 
 // ---------------------------------------------------------------------------
-// Learned distance table of each learned particle over its coupling box:
-// tables[pid * cap + lx + sx (ly + sy lz)] = R_c net(R^T (x - X) / R_c).
-// grid = (ceil(cap / 64), n); one wave evaluates 64 cells as four 16-cell tiles.
+// Learned distance table of each learned particle over its coupling box,
+// tables[pid * cap + lx + sx (ly + sy lz)]: the network is queried only on the
+// shell r_in - eps/2 <= |x - X| <= R_c + eps/2 (r_in the inscribed radius);
+// inside it the entry is R_c net(R^T (x - X) / R_c), below it -1e30 (certainly
+// inside, B = 1), above it +1e30 (certainly outside, B = 0) -- the same
+// early-outs the lattice kernel applies before reading the table.
+// grid = (ceil(cap / TAB_CHUNK), n), one wave per chunk of TAB_CHUNK cells: the
+// chunk's shell cells are compacted in LDS and evaluated in 16-cell tiles.
 // ---------------------------------------------------------------------------
+constexpr int TAB_CHUNK = 256;
+
 __global__ __launch_bounds__(64) void k_mlp_table(Lattice L, const DevParticle *__restrict__ parts,
                                                   const float *th_cube, const __bf16 *pk_cube, const float *th_sph,
                                                   const __bf16 *pk_sph, float *__restrict__ tables, long long cap) {
+  __shared__ int qidx[TAB_CHUNK];
+  __shared__ float qx[3][TAB_CHUNK];
   const int pid = blockIdx.y;
   const DevParticle &p = parts[pid];
   if (!p.learned) return;
   const int sx = p.hi[0] - p.lo[0] + 1, sy = p.hi[1] - p.lo[1] + 1, sz = p.hi[2] - p.lo[2] + 1;
   const int total = sx * sy * sz;
-  const int base = blockIdx.x * 64;
+  const int base = blockIdx.x * TAB_CHUNK;
   if (base >= total) return;
   const MlpArgs A = mlp_args(p.shape == 1 ? th_cube : th_sph, p.shape == 1 ? pk_cube : pk_sph);
   const int l = threadIdx.x, g = l >> 4, li = l & 15;
-  const int nn[3] = {L.nx, L.ny, L.nz};
-  const double inv = 1.0 / p.rc;
-  for (int q = 0; q < 4; ++q) {
-    const int idx = base + q * 16 + li;
-    const bool ok = idx < total;
-    float x[3] = {0.f, 0.f, 0.f};
-    if (ok) {
-      const int loc[3] = {idx % sx, (idx / sx) % sy, idx / (sx * sy)};
-      double d[3];
-      for (int k = 0; k < 3; ++k) {
-        int v = p.lo[k] + loc[k];
-        if (!L.bc[k]) { v %= nn[k]; if (v < 0) v += nn[k]; }
-        double dv = (v + 0.5) - p.X[k];
-        if (!L.bc[k]) {
-          const double h = 0.5 * nn[k];
-          if (dv > h) dv -= nn[k];
-          else if (dv < -h) dv += nn[k];
-        }
-        d[k] = dv;
+  const double rc = p.rc, inv = 1.0 / rc;
+  const double rin = p.shape == 2 ? fmin(p.prm[0], p.prm[1]) : p.prm[0];
+  const double lo2 = rin - 0.5 * L.eps, hi2 = rc + 0.5 * L.eps;
+  float *tab = tables + (size_t)pid * cap;
+  // classify; compact the shell cells (in cell order)
+  int nq = 0;  // wave-uniform
+  for (int k = 0; k < TAB_CHUNK / 64; ++k) {
+    const int idx = base + k * 64 + l;
+    bool shell = false;
+    float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+    if (idx < total) {
+      // box cells are unwrapped, so x - X needs no minimum image
+      const double d0 = (p.lo[0] + idx % sx + 0.5) - p.X[0];
+      const double d1 = (p.lo[1] + (idx / sx) % sy + 0.5) - p.X[1];
+      const double d2 = (p.lo[2] + idx / (sx * sy) + 0.5) - p.X[2];
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      if (r2 > hi2 * hi2) {
+        tab[idx] = 1e30f;
+      } else if (lo2 > 0.0 && r2 < lo2 * lo2) {
+        tab[idx] = -1e30f;
+      } else {
+        shell = true;
+        const double *R = p.R;
+        b0 = (float)((R[0] * d0 + R[3] * d1 + R[6] * d2) * inv);
+        b1 = (float)((R[1] * d0 + R[4] * d1 + R[7] * d2) * inv);
+        b2 = (float)((R[2] * d0 + R[5] * d1 + R[8] * d2) * inv);
       }
-      for (int k = 0; k < 3; ++k)
-        x[k] = (float)((p.R[0 * 3 + k] * d[0] + p.R[1 * 3 + k] * d[1] + p.R[2 * 3 + k] * d[2]) * inv);
     }
-    float z1[16], z2[16], z3[16], y;
-    mlp_forward_tile(A, x[0], x[1], x[2], z1, z2, z3, y);
-    if (ok && g == 0) tables[(size_t)pid * cap + idx] = (float)(y * p.rc);
+    const unsigned long long mask = __ballot(shell);
+    if (shell) {
+      const int slot = nq + __popcll(mask & ((1ull << l) - 1ull));
+      qidx[slot] = idx;
+      qx[0][slot] = b0;
+      qx[1][slot] = b1;
+      qx[2][slot] = b2;
+    }
+    nq += __popcll(mask);
+  }
+  __syncthreads();
+  // evaluate 64 shell cells per pass as four 16-cell tiles
+  for (int t0 = 0; t0 < nq; t0 += 64) {
+    for (int q = 0; q < 4; ++q) {
+      const int k = t0 + q * 16 + li;
+      const bool ok = k < nq;
+      const float x0 = ok ? qx[0][k] : 0.f, x1 = ok ? qx[1][k] : 0.f, x2 = ok ? qx[2][k] : 0.f;
+      float z1[16], z2[16], z3[16], y;
+      mlp_forward_tile(A, x0, x1, x2, z1, z2, z3, y);
+      if (ok && g == 0) tab[qidx[k]] = (float)(y * rc);
+    }
   }
 }
 
@@ -400,7 +432,8 @@ hipError_t launch_mlp_table(const Lattice &L, const DevParticle *parts, int n, c
                             const __bf16 *packed_cube, const float *theta_sph, const __bf16 *packed_sph,
                             float *tables, long long cap, hipStream_t s) {
   if (n <= 0 || !tables) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_table, dim3((unsigned)((cap + 63) / 64), n), dim3(64), 0, s, L, parts, theta_cube,
+  hipLaunchKernelGGL(k_mlp_table, dim3((unsigned)((cap + TAB_CHUNK - 1) / TAB_CHUNK), n), dim3(64), 0, s, L, parts,
+                     theta_cube,
                      packed_cube, theta_sph, packed_sph, tables, cap);
   return hipGetLastError();
 }

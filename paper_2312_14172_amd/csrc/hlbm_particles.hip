@@ -1,0 +1,497 @@
+// hlbm_particles.hip -- gfx950 kernels of the particle side of the HLBM time
+// step: particle set-up, binning into tile lists, momentum exchange and the
+// FP64 equations of motion.
+//
+// Per step (Sec. 4.2 time-step order), before the lattice kernel:
+//   k_mea      one workgroup per (particle, slab of z-layers of its bounding
+//              box): momentum exchange over the slab's inside cells (compacted
+//              in LDS), read in pull form from the stored state, FP64 shuffle
+//              reduction to a slab record;
+//   k_eom_bin  one workgroup per particle: the slab records summed in a fixed
+//              order, gravity and buoyancy, Newton-Euler and quaternion update
+//              in FP64, then the particle appended to the tile lists of its new
+//              coupling box (tiles of 64 x 4 x 4 cells).
+#include "hlbm_device.h"
+#include "hlbm_internal.h"
+
+namespace hlbm {
+
+
+
+// ---------------------------------------------------------------------------
+// Particle geometry on the device
+// ---------------------------------------------------------------------------
+__device__ inline void quat_rot(const double *q, double *R) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+__device__ inline double circumradius(int shape, double p0, double p1) {
+  if (shape == 0) return p0;
+  if (shape == 1) return 1.7320508075688772 * (p0 - p1) + p1;
+  return fmax(p0, p1);
+}
+
+// Cells whose centre lies within `reach` of X along each axis, clipped on
+// wall axes (unwrapped coordinates on periodic axes).
+__device__ inline void cell_box(const Lattice &L, const double *X, double reach, int *lo, int *hi) {
+  const int n[3] = {L.nx, L.ny, L.nz};
+  for (int k = 0; k < 3; ++k) {
+    int a = (int)ceil(X[k] - reach - 0.5);
+    int b = (int)floor(X[k] + reach - 0.5);
+    if (L.bc[k]) {
+      a = max(a, 0);
+      b = min(b, n[k] - 1);
+    }
+    lo[k] = a;
+    hi[k] = b;
+  }
+}
+
+// Coupling box: the cells that can have B > 0 (centre within rc + eps/2).
+__device__ inline void particle_boxes(const Lattice &L, DevParticle &p) {
+  cell_box(L, p.X, p.rc + 0.5 * L.eps + 1e-9, p.lo, p.hi);
+}
+
+__device__ inline void derive(const Lattice &L, DevParticle &p) {
+  quat_rot(p.q, p.R);
+  p.rc = circumradius(p.shape, p.prm[0], p.prm[1]);
+  particle_boxes(L, p);
+}
+
+__global__ void k_prepare(Lattice L, const hlbm_particle *in, DevParticle *out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const hlbm_particle s = in[i];
+  DevParticle p;
+  for (int k = 0; k < 3; ++k) {
+    p.X[k] = s.pos[k]; p.U[k] = s.vel[k]; p.W[k] = s.omega[k];
+    p.I[k] = s.inertia[k]; p.prm[k] = s.param[k];
+    p.Fh[k] = 0.0; p.Th[k] = 0.0;
+  }
+  const double nq = sqrt(s.quat[0] * s.quat[0] + s.quat[1] * s.quat[1] + s.quat[2] * s.quat[2] +
+                         s.quat[3] * s.quat[3]);
+  for (int k = 0; k < 4; ++k) p.q[k] = s.quat[k] / nq;
+  p.m = s.mass;
+  p.V = s.volume;
+  p.shape = s.shape;
+  p.flags = s.flags;
+  p.learned = 0;
+  derive(L, p);
+  out[i] = p;
+}
+
+// Mark the particles whose shape family uses its learned indicator (and whose
+// aspect matches the trained one).
+__global__ void k_mark_learned(DevParticle *parts, int n, int mode_cube, double aspect_cube, int mode_sph,
+                               double aspect_sph) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  DevParticle &p = parts[i];
+  const double asp = p.prm[1] / p.prm[0];
+  int on = 0;
+  if (p.shape == 1 && mode_cube) on = fabs(asp - aspect_cube) <= 1e-6 * aspect_cube;
+  if (p.shape == 2 && mode_sph) on = fabs(asp - aspect_sph) <= 1e-6 * aspect_sph;
+  p.learned = on;
+}
+
+__global__ void k_fill_int(int *p, int v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// One thread per (particle, tile of its coupling box): append the particle to
+// the tile's list.  grid = (ceil(cap / 64), n).
+__global__ void k_bin(Lattice L, const DevParticle *parts, int *tcnt, int *tlist, int *status) {
+  const int pid = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const DevParticle &p = parts[pid];
+  int tx[MAX_AXIS_TILES], ty[MAX_AXIS_TILES], tz[MAX_AXIS_TILES];
+  const int cx = axis_tiles(p.lo[0], p.hi[0], L.nx, !L.bc[0], TX, tx);
+  const int cy = axis_tiles(p.lo[1], p.hi[1], L.ny, !L.bc[1], TY, ty);
+  const int cz = axis_tiles(p.lo[2], p.hi[2], L.nz, !L.bc[2], TZ, tz);
+  if (k >= cx * cy * cz) return;
+  const int a = k % cx, b = (k / cx) % cy, c = k / (cx * cy);
+  const int t = tx[a] + L.ntx * (ty[b] + L.nty * tz[c]);
+  const int slot = atomicAdd(&tcnt[t], 1);
+  if (slot < MAXC) tlist[t * MAXC + slot] = pid;
+  else atomicOr(status, ST_TILE_OVERFLOW);
+}
+
+// ---------------------------------------------------------------------------
+// Fluid -> particle (momentum exchange) and equations of motion
+// ---------------------------------------------------------------------------
+__device__ inline void cross_sub(const double *a, const double *b, double *o) {
+  o[0] -= a[1] * b[2] - a[2] * b[1];
+  o[1] -= a[2] * b[0] - a[0] * b[2];
+  o[2] -= a[0] * b[1] - a[1] * b[0];
+}
+
+// Momentum exchange (Sec. 3.2 MEA, force and torque equations) over the cells
+// x_b whose centre is inside the particle, from the stored state of time t in
+// pull storage:
+//   f_i(x_b + c_i, t) = A[i][x_b],  f_opp(i)(x_b, t) = A[opp i][x_b + c_i],
+//   F_h(x_b) = sum_i (c_i - u_p(x_b)) f_i(x_b + c_i) + (c_i + u_p(x_b)) f_opp(i)(x_b)
+// (directions whose neighbour lies past a wall are skipped).  The force on the
+// particle is -sum F_h, the torque -sum (x_b - X) x F_h.
+//
+// One workgroup per (particle, slab of MEA_LAYERS z-layers of its bounding
+// box).  The slab's cells are classified 256 at a time; the inside ones are
+// compacted into an LDS queue (in cell order, which keeps the x-runs of a
+// convex body contiguous for the loads) and drained 256 at a time, so the 36
+// population loads and the FP64 sums run on full wavefronts.  Each thread
+// accumulates its cells in queue order; the slab's sum is reduced with a fixed
+// wavefront-shuffle tree in FP64 and written as one record.
+constexpr int MEA_LAYERS = 4;
+
+// A cell of the slab, as box-relative coordinates packed in one int
+// (x | y << 8 | z << 16, each < 256), its wrapped lattice coordinates and its
+// offset from the particle centre (formed from the unwrapped coordinate, which
+// is the minimum image: the box is narrower than half a periodic extent).
+struct MeaBox {
+  int lo[3], sx, sy, nl;
+  double X[3];
+};
+
+__device__ inline void mea_cell(const Lattice &L, const MeaBox &g, int packed, int *c, double *d) {
+  const int nn[3] = {L.nx, L.ny, L.nz};
+  const int r[3] = {packed & 255, (packed >> 8) & 255, packed >> 16};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int u = g.lo[k] + r[k];
+    int v = u;
+    if (!L.bc[k]) v = v >= nn[k] ? v - nn[k] : (v < 0 ? v + nn[k] : v);
+    c[k] = v;
+    d[k] = (u + 0.5) - g.X[k];
+  }
+}
+
+// Population load at a 32-bit byte offset from a wavefront-uniform plane base
+// (O32: the host has checked that every offset fits), else 64-bit indexing.
+template <bool O32, typename S>
+__device__ inline S mea_load(const S *__restrict__ plane, unsigned cell) {
+  if constexpr (O32) return *(const S *)((const char *)plane + (cell * (unsigned)sizeof(S)));
+  else return plane[cell];
+}
+
+// One inside cell's F_h, added as -F_h and -(x_b - X) x F_h.  With the stored
+// relative deviations s = K (f - w) / w of f_i(x_b + c_i) and f_opp(i)(x_b):
+//   (c - u) f_in + (c + u) f_out = c w (2 + (s_in + s_out) / K) - u w (s_in - s_out) / K.
+template <class ST, bool O32>
+__device__ inline void mea_accumulate(const Lattice &L, const typename ST::S *__restrict__ A, const int *c,
+                                      const double *d, const double *U, const double *W, double *F, double *T) {
+  using S = typename ST::S;
+  const double upx = U[0] + W[1] * d[2] - W[2] * d[1];
+  const double upy = U[1] + W[2] * d[0] - W[0] * d[2];
+  const double upz = U[2] + W[0] * d[1] - W[1] * d[0];
+  const unsigned sxy = (unsigned)L.nx * (unsigned)L.ny;
+  const unsigned cell = (unsigned)c[0] + (unsigned)L.nx * (unsigned)c[1] + sxy * (unsigned)c[2];
+  const int xm = c[0] == 0 ? L.nx - 1 : c[0] - 1, xp = c[0] == L.nx - 1 ? 0 : c[0] + 1;
+  const int ym = c[1] == 0 ? L.ny - 1 : c[1] - 1, yp = c[1] == L.ny - 1 ? 0 : c[1] + 1;
+  const int zm = c[2] == 0 ? L.nz - 1 : c[2] - 1, zp = c[2] == L.nz - 1 ? 0 : c[2] + 1;
+  const bool okxm = !(L.bc[0] && c[0] == 0), okxp = !(L.bc[0] && c[0] == L.nx - 1);
+  const bool okym = !(L.bc[1] && c[1] == 0), okyp = !(L.bc[1] && c[1] == L.ny - 1);
+  const bool okzm = !(L.bc[2] && c[2] == 0), okzp = !(L.bc[2] && c[2] == L.nz - 1);
+  const double invK = 1.0 / (double)ST::K();
+  double h[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int ex = kCX[i] == 1 ? xp : (kCX[i] == -1 ? xm : c[0]);
+    const int ey = kCY[i] == 1 ? yp : (kCY[i] == -1 ? ym : c[1]);
+    const int ez = kCZ[i] == 1 ? zp : (kCZ[i] == -1 ? zm : c[2]);
+    const bool ok = (kCX[i] == 1 ? okxp : (kCX[i] == -1 ? okxm : true)) &&
+                    (kCY[i] == 1 ? okyp : (kCY[i] == -1 ? okym : true)) &&
+                    (kCZ[i] == 1 ? okzp : (kCZ[i] == -1 ? okzm : true));
+    const unsigned nb = (unsigned)ex + (unsigned)L.nx * (unsigned)ey + sxy * (unsigned)ez;
+    const S *__restrict__ Ain = A + (size_t)i * (size_t)L.N;
+    const S *__restrict__ Aout = A + (size_t)opp(i) * (size_t)L.N;
+    const double sin_ = (double)ST::dec(mea_load<O32>(Ain, cell));
+    const double sout = (double)ST::dec(mea_load<O32>(Aout, nb));
+    const double w = ok ? wgt(i) : 0.0;
+    const double sum = w * (2.0 + (sin_ + sout) * invK);
+    const double dif = w * ((sin_ - sout) * invK);
+    if (kCX[i] != 0) h[0] += kCX[i] > 0 ? sum : -sum;
+    if (kCY[i] != 0) h[1] += kCY[i] > 0 ? sum : -sum;
+    if (kCZ[i] != 0) h[2] += kCZ[i] > 0 ? sum : -sum;
+    h[0] -= upx * dif;
+    h[1] -= upy * dif;
+    h[2] -= upz * dif;
+  }
+  F[0] -= h[0]; F[1] -= h[1]; F[2] -= h[2];
+  cross_sub(d, h, T);
+}
+
+// Equations of motion of one particle in FP64 with dt = 1 (Sec. 2.2; Sec. 5.1
+// for the external force), from its hydrodynamic force and torque Fs:
+//   U <- U + (F + (m - rho_f V) g) / m;  X <- X + U (wrapped on periodic axes);
+//   w_b <- w_b + I^-1 (T_b - w_b x I w_b) in the body frame;
+//   q <- normalize(q (x) exp(w_b / 2));  w <- R(q) w_b;
+// and the new coupling box.  Particles with m <= 0 are held fixed.
+__device__ inline void advance_particle(const Lattice &L, DevParticle &p, const double *Fs, int *status) {
+  const int nn[3] = {L.nx, L.ny, L.nz};
+  for (int k = 0; k < 3; ++k) { p.Fh[k] = Fs[k]; p.Th[k] = Fs[3 + k]; }
+  if (p.m > 0.0) {
+    const double buoy = p.m - L.rho_f * p.V;
+    for (int k = 0; k < 3; ++k) {
+      p.U[k] += (Fs[k] + buoy * L.g[k]) / p.m;
+      p.X[k] += p.U[k];
+      if (!L.bc[k]) {
+        if (p.X[k] >= nn[k]) p.X[k] -= nn[k];
+        else if (p.X[k] < 0.0) p.X[k] += nn[k];
+      } else if (!(p.X[k] >= 0.0 && p.X[k] <= nn[k])) {
+        atomicOr(status, ST_WALL_EXIT);
+      }
+    }
+    const double *R = p.R;
+    double wb[3], tb[3];
+    for (int k = 0; k < 3; ++k) {
+      wb[k] = R[0 * 3 + k] * p.W[0] + R[1 * 3 + k] * p.W[1] + R[2 * 3 + k] * p.W[2];
+      tb[k] = R[0 * 3 + k] * Fs[3] + R[1 * 3 + k] * Fs[4] + R[2 * 3 + k] * Fs[5];
+    }
+    const double Iw0 = p.I[0] * wb[0], Iw1 = p.I[1] * wb[1], Iw2 = p.I[2] * wb[2];
+    const double g0 = wb[1] * Iw2 - wb[2] * Iw1;
+    const double g1 = wb[2] * Iw0 - wb[0] * Iw2;
+    const double g2 = wb[0] * Iw1 - wb[1] * Iw0;
+    wb[0] += (tb[0] - g0) / p.I[0];
+    wb[1] += (tb[1] - g1) / p.I[1];
+    wb[2] += (tb[2] - g2) / p.I[2];
+    const double ang = sqrt(wb[0] * wb[0] + wb[1] * wb[1] + wb[2] * wb[2]);
+    double d0 = 1.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+    if (ang > 0.0) {
+      double sn, cs;
+      sincos(0.5 * ang, &sn, &cs);
+      const double f = sn / ang;
+      d0 = cs; d1 = f * wb[0]; d2 = f * wb[1]; d3 = f * wb[2];
+    }
+    const double *q = p.q;
+    const double qn[4] = {q[0] * d0 - q[1] * d1 - q[2] * d2 - q[3] * d3,
+                          q[0] * d1 + q[1] * d0 + q[2] * d3 - q[3] * d2,
+                          q[0] * d2 - q[1] * d3 + q[2] * d0 + q[3] * d1,
+                          q[0] * d3 + q[1] * d2 - q[2] * d1 + q[3] * d0};
+    const double nq = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+    for (int k = 0; k < 4; ++k) p.q[k] = qn[k] / nq;
+    quat_rot(p.q, p.R);
+    for (int k = 0; k < 3; ++k)
+      p.W[k] = p.R[k * 3 + 0] * wb[0] + p.R[k * 3 + 1] * wb[1] + p.R[k * 3 + 2] * wb[2];
+    if (!(p.X[0] == p.X[0] && p.X[1] == p.X[1] && p.X[2] == p.X[2])) atomicOr(status, ST_UNSTABLE);
+    particle_boxes(L, p);
+  }
+}
+
+// Number of MEA_LAYERS-slabs of a momentum-exchange box (at least one: an empty
+// box still writes a zero record).
+__device__ inline int mea_slabs(int lo2, int hi2) {
+  return hi2 < lo2 ? 1 : (hi2 - lo2 + MEA_LAYERS) / MEA_LAYERS;
+}
+
+// Momentum exchange of one slab: workgroup (order[x], slab) reduces the slab's
+// inside cells into one record partial[pid][slab][F, T].  The slab is
+// classified in rounds: each wavefront takes 64 / sx whole x-rows (lane ->
+// (x, row)), the inside cells are compacted into the LDS queue, and full
+// queues of 256 cells are drained by all threads at once.
+template <class ST, bool O32>
+__global__ __launch_bounds__(256) void k_mea(Lattice L, const typename ST::S *__restrict__ A,
+                                             const DevParticle *__restrict__ parts, const int *__restrict__ order,
+                                             int lmax, double *__restrict__ partial) {
+  __shared__ int queue[512];
+  __shared__ int wcnt[4];
+  __shared__ double red[4][6];
+  const int pid = order[blockIdx.x];
+  const int slab = blockIdx.y;
+  const DevParticle &sp = parts[pid];
+  MeaBox g;
+  int hi[3];
+  cell_box(L, sp.X, sp.rc + 1e-9, g.lo, hi);
+  const int nslab = mea_slabs(g.lo[2], hi[2]);
+  if (slab >= nslab) return;   // uniform per workgroup
+  g.lo[2] += slab * MEA_LAYERS;
+  g.sx = hi[0] - g.lo[0] + 1;
+  g.sy = hi[1] - g.lo[1] + 1;
+  g.nl = min(MEA_LAYERS, hi[2] - g.lo[2] + 1);
+  for (int k = 0; k < 3; ++k) g.X[k] = sp.X[k];
+  const int shape = sp.shape;
+  const double p0 = sp.prm[0], p1 = sp.prm[1];
+  const double U[3] = {sp.U[0], sp.U[1], sp.U[2]};
+  const double W[3] = {sp.W[0], sp.W[1], sp.W[2]};
+  double R[9];
+  for (int k = 0; k < 9; ++k) R[k] = sp.R[k];
+  const int learned = sp.learned && L.tables;
+  const int tsx = sp.hi[0] - sp.lo[0] + 1, tsy = sp.hi[1] - sp.lo[1] + 1;
+  const int t = threadIdx.x, w = wave_id(), lane = lane_id();
+  const int rows = (g.sx > 0 && g.sy > 0 && g.nl > 0) ? g.sy * g.nl : 0;  // sx <= 64 (host check)
+  const int sxp = rows > 0 ? g.sx : 64;
+  const int rpw = 64 / sxp;     // rows per wavefront and round
+  const int rx = lane % sxp, rsub = lane / sxp;
+  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  int queued = 0;  // uniform
+  for (int r0 = 0; r0 < rows; r0 += 4 * rpw) {
+    const int row = r0 + w * rpw + rsub;
+    bool in = false;
+    int packed = 0;
+    if (rsub < rpw && row < rows) {
+      const int ry = row % g.sy, rz = row / g.sy;
+      packed = rx | (ry << 8) | (rz << 16);
+      int c[3];
+      double d[3];
+      mea_cell(L, g, packed, c, d);
+      if (learned) {
+        const int lx = g.lo[0] + rx - sp.lo[0], ly = g.lo[1] + ry - sp.lo[1], lz = g.lo[2] + rz - sp.lo[2];
+        in = L.tables[(size_t)pid * L.table_cap + lx + tsx * (ly + tsy * lz)] <= 0.0f;
+      } else {
+        double b[3] = {d[0], d[1], d[2]};
+        if (shape != 0) {
+          b[0] = R[0] * d[0] + R[3] * d[1] + R[6] * d[2];
+          b[1] = R[1] * d[0] + R[4] * d[1] + R[7] * d[2];
+          b[2] = R[2] * d[0] + R[5] * d[1] + R[8] * d[2];
+        }
+        in = inside_body(shape, p0, p1, b[0], b[1], b[2]);
+      }
+    }
+    const unsigned long long mask = __ballot(in);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[w] = __popcll(mask);
+    __syncthreads();
+    int off = queued, added = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      off += (k < w) ? wcnt[k] : 0;
+      added += wcnt[k];
+    }
+    if (in) queue[off + before] = packed;
+    queued += added;
+    __syncthreads();
+    if (queued >= 256) {
+      int c[3];
+      double d[3];
+      mea_cell(L, g, queue[t], c, d);
+      mea_accumulate<ST, O32>(L, A, c, d, U, W, F, T);
+      const int rest = queued - 256;
+      const int keep = t < rest ? queue[256 + t] : 0;
+      __syncthreads();
+      if (t < rest) queue[t] = keep;
+      queued = rest;
+      __syncthreads();
+    }
+  }
+  if (t < queued) {
+    int c[3];
+    double d[3];
+    mea_cell(L, g, queue[t], c, d);
+    mea_accumulate<ST, O32>(L, A, c, d, U, W, F, T);
+  }
+  double v[6] = {F[0], F[1], F[2], T[0], T[1], T[2]};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[w][k] = v[k];
+  }
+  __syncthreads();
+  if (t < 6) partial[((size_t)pid * lmax + slab) * 6 + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+}
+
+// One 64-thread workgroup per particle: the slab records of k_mea loaded in
+// parallel and summed in slab order (thread t sums slabs t, t + 64, ...; the
+// 64 partial sums are added in order), the equations of motion, then the
+// particle appended to the tile lists of its new coupling box.
+__global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restrict__ parts, int lmax,
+                                                const double *__restrict__ partial, int *tcnt, int *tlist,
+                                                int *status) {
+  __shared__ double red[64][6];
+  __shared__ int ts[3][MAX_AXIS_TILES];
+  __shared__ int tn[3];
+  const int pid = blockIdx.x;
+  const int t = threadIdx.x;
+  int lo[3], hi[3];
+  cell_box(L, parts[pid].X, parts[pid].rc + 1e-9, lo, hi);
+  const int nrec = mea_slabs(lo[2], hi[2]);
+  const double *src = partial + (size_t)pid * lmax * 6;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int r = t; r < nrec; r += 64)
+    for (int k = 0; k < 6; ++k) acc[k] += src[r * 6 + k];
+  for (int k = 0; k < 6; ++k) red[t][k] = acc[k];
+  __syncthreads();
+  if (t == 0) {
+    double Fs[6] = {0, 0, 0, 0, 0, 0};
+    for (int l = 0; l < 64; ++l)
+      for (int k = 0; k < 6; ++k) Fs[k] += red[l][k];
+    DevParticle p = parts[pid];
+    advance_particle(L, p, Fs, status);
+    parts[pid] = p;
+    tn[0] = axis_tiles(p.lo[0], p.hi[0], L.nx, !L.bc[0], TX, ts[0]);
+    tn[1] = axis_tiles(p.lo[1], p.hi[1], L.ny, !L.bc[1], TY, ts[1]);
+    tn[2] = axis_tiles(p.lo[2], p.hi[2], L.nz, !L.bc[2], TZ, ts[2]);
+  }
+  __syncthreads();
+  const int cx = tn[0], cy = tn[1], cz = tn[2];
+  for (int k = t; k < cx * cy * cz; k += 64) {
+    const int a = k % cx, b = (k / cx) % cy, c = k / (cx * cy);
+    const int tile = ts[0][a] + L.ntx * (ts[1][b] + L.nty * ts[2][c]);
+    const int slot = atomicAdd(&tcnt[tile], 1);
+    if (slot < MAXC) tlist[tile * MAXC + slot] = pid;
+    else atomicOr(status, ST_TILE_OVERFLOW);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+static inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b); }
+
+#define HLBM_DISPATCH(prec, CALL)                       \
+  switch (prec) {                                       \
+    case 0: { using ST = StoreF64; CALL; } break;       \
+    case 1: { using ST = StoreF32; CALL; } break;       \
+    default: { using ST = StoreF16S; CALL; } break;     \
+  }
+
+hipError_t launch_prepare(const Lattice &L, const hlbm_particle *in, DevParticle *out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prepare, dim3(blocks_for(n, 128)), dim3(128), 0, s, L, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_learned(DevParticle *parts, int n, int mode_cube, double aspect_cube, int mode_sph,
+                               double aspect_sph, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_learned, dim3(blocks_for(n, 128)), dim3(128), 0, s, parts, n, mode_cube, aspect_cube,
+                     mode_sph, aspect_sph);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int v, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int cap, int *tcnt, int *tlist,
+                      int *status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bin, dim3(blocks_for(cap, 64), n), dim3(64), 0, s, L, parts, tcnt, tlist, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevParticle *parts, const int *order, int n,
+                      int lmax, double *partial, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid(n, (lmax + MEA_LAYERS - 1) / MEA_LAYERS);
+  HLBM_DISPATCH(prec, {
+    if ((unsigned long long)L.N * sizeof(typename ST::S) < (1ull << 32))
+      hipLaunchKernelGGL((k_mea<ST, true>), grid, dim3(256), 0, s, L, (const typename ST::S *)A, parts, order, lmax, partial);
+    else
+      hipLaunchKernelGGL((k_mea<ST, false>), grid, dim3(256), 0, s, L, (const typename ST::S *)A, parts, order, lmax, partial);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, const double *partial,
+                          int *tcnt, int *tlist, int *status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eom_bin, dim3(n), dim3(64), 0, s, L, parts, lmax, partial, tcnt, tlist, status);
+  return hipGetLastError();
+}
+
+}  // namespace hlbm

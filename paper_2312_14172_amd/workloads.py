@@ -194,6 +194,77 @@ def rsa_positions(rng, radii, n, bc, gap=1.0, wall_margin=1.0, batch=64, max_att
 
 
 # ---------------------------------------------------------------------------
+# Random sequential addition on a voxel-occupancy grid (true shapes)
+# ---------------------------------------------------------------------------
+def _rotation(q):
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _footprint(shape, prm, q, frac, grow):
+    """Offsets (relative to floor(X)) of the cells whose centre lies in the
+    shape grown by `grow` (a superset of its grow-neighbourhood for the
+    spheroid), for a centre at floor(X) + frac.  Placement geometry only."""
+    reach = circumradius(shape, prm) + grow
+    k = int(math.ceil(reach)) + 1
+    ax = np.arange(-k, k + 1)
+    gz, gy, gx = np.meshgrid(ax, ax, ax, indexing="ij")
+    off = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+    d = off + 0.5 - np.asarray(frac)
+    b = d @ _rotation(q)  # body-frame coordinates R^T d, row-wise
+    if shape == SPHERE:
+        inside = np.sum(b * b, axis=1) <= (prm[0] + grow) ** 2
+    elif shape == ROUNDED_CUBE:
+        core = prm[0] - prm[1]
+        o = np.maximum(np.abs(b) - core, 0.0)
+        inside = np.sum(o * o, axis=1) <= (prm[1] + grow) ** 2
+    else:
+        a, c = prm[0] + grow, prm[1] + grow
+        inside = (b[:, 0] / a) ** 2 + (b[:, 1] ** 2 + b[:, 2] ** 2) / c ** 2 <= 1.0
+    return off[inside]
+
+
+def voxel_rsa_positions(rng, shapes, prms, quats, n, bc, gap=1.0, wall_margin=1.0, max_attempts=20_000_000):
+    """Place the given oriented shapes (in the given order) uniformly at random
+    so that their footprints grown by gap/2 occupy disjoint cells of the
+    lattice (surface gap >= gap at lattice resolution), wrapping on periodic
+    axes and keeping every footprint cell at least wall_margin cells from a
+    wall."""
+    n = tuple(int(v) for v in n)
+    occ = np.zeros(n[::-1], dtype=bool)  # [z, y, x]
+    pos = np.zeros((len(shapes), 3))
+    attempts = 0
+    for i in range(len(shapes)):
+        shape, prm, q = int(shapes[i]), prms[i], quats[i]
+        reach = circumradius(shape, prm) + 0.5 * gap
+        lo = np.array([0.0 if bc[k] == 0 else reach + wall_margin for k in range(3)])
+        hi = np.array([float(n[k]) if bc[k] == 0 else n[k] - reach - wall_margin for k in range(3)])
+        while True:
+            attempts += 1
+            if attempts > max_attempts:
+                raise RuntimeError(f"voxel RSA stalled after placing {i} of {len(shapes)}")
+            X = lo + (hi - lo) * rng.random(3)
+            base = np.floor(X).astype(int)
+            if occ[base[2] % n[2], base[1] % n[1], base[0] % n[0]]:
+                continue
+            cells = _footprint(shape, prm, q, X - base, 0.5 * gap) + base
+            ok = True
+            for k in range(3):
+                if bc[k] == 0:
+                    cells[:, k] %= n[k]
+                elif cells[:, k].min() < wall_margin or cells[:, k].max() > n[k] - 1 - wall_margin:
+                    ok = False
+            if not ok or occ[cells[:, 2], cells[:, 1], cells[:, 0]].any():
+                continue
+            occ[cells[:, 2], cells[:, 1], cells[:, 0]] = True
+            pos[i] = X
+            break
+    return pos
+
+
+# ---------------------------------------------------------------------------
 # Workloads
 # ---------------------------------------------------------------------------
 @dataclass
@@ -276,6 +347,30 @@ def mixed_shapes(n=256, count=2000, r_eq=6.0, seed=3, tau=0.6, steps=1000, preci
     return w
 
 
+def hindered_settling(n=384, count=11265, r_eq_range=(4.0, 8.0), seed=5, tau=0.55, steps=5000,
+                      precision="fp32", density_ratio=2.5, gap=1.0):
+    """Hindered settling: spheres, rounded cubes and prolate 2:1 spheroids in
+    equal thirds with equivalent radius r_eq ~ U[4, 8] (solid fraction ~0.2 at
+    11 265 particles in 384^3), uniformly random orientations, voxel-occupancy
+    RSA with surface gap >= 1, z walls, tau = 0.55, density ratio 2.5."""
+    rng = np.random.default_rng(seed)
+    shapes = np.array([SPHERE, ROUNDED_CUBE, SPHEROID] * (count // 3 + 1))[:count]
+    req = rng.uniform(r_eq_range[0], r_eq_range[1], count)
+    prms = [equal_volume_params(int(s), float(r)) for s, r in zip(shapes, req)]
+    rcirc = np.array([circumradius(int(s), p) for s, p in zip(shapes, prms)])
+    quats = [shoemake_quaternion(rng) for _ in range(count)]
+    order = np.argsort(-rcirc, kind="stable")
+    pos = voxel_rsa_positions(rng, shapes[order], [prms[i] for i in order], [quats[i] for i in order],
+                              (n, n, n), (0, 0, 1), gap=gap)
+    recs = [make_particle(int(shapes[i]), prms[i], pos[k], quat=quats[i], density_ratio=density_ratio)
+            for k, i in enumerate(order)]
+    w = Workload(f"hindered{n}", (n, n, n), (0, 0, 1), tau, steps, precision, seed=seed,
+                 density_ratio=density_ratio,
+                 description=f"{n}^3, z walls, {count} mixed shapes r_eq~U{r_eq_range}, tau={tau}")
+    w.particles = np.array(recs)
+    return w
+
+
 def smooth_fields(n, seed, rho_amp=1e-3, u_amp=1e-2, modes=3):
     """Smooth periodic random density and velocity fields (sums of a few
     Fourier modes with seeded amplitudes and phases).  Returns rho[N], u[3,N]
@@ -323,7 +418,8 @@ def get(name: str, **kw) -> Workload:
     sphere32   -- 32^3 periodic, one sphere (parity case);
     spheres128 -- 128^3, z walls, 200 spheres r~U[5,7], tau 0.6;
     mixed256   -- 256^3, z walls, 2000 mixed shapes r_eq 6, tau 0.6;
-    mixed256_learned -- as mixed256 with the learned indicator for non-spheres.
+    mixed256_learned -- as mixed256 with the learned indicator for non-spheres;
+    hindered384 -- 384^3, z walls, 11 265 mixed shapes r_eq~U[4,8], tau 0.55.
     """
     if name == "sphere32":
         return single_sphere(**kw)
@@ -333,6 +429,8 @@ def get(name: str, **kw) -> Workload:
         return mixed_shapes(**kw)
     if name == "mixed256_learned":
         return mixed_shapes(learned=True, **kw)
+    if name == "hindered384":
+        return hindered_settling(**kw)
     raise KeyError(name)
 
 

@@ -1,0 +1,113 @@
+"""Full-size parity: the settling-spheres (128^3, 200 spheres) and mixed-shape
+(256^3, 2000 particles) workloads at their real sizes, in the precisions the
+benchmark runs them in and in FP64, against the FP64 CPU oracle over a few
+steps from a non-trivial state (smooth random density and velocity, particles
+moving and spinning).  Every cell's fields and every particle's force, torque
+and state are compared; the steps are split across calls so that the first
+step of each call after hlbm_set_particles and later steps are both covered.
+
+Tolerances as in test_gpu_parity: FP64 -- velocity L2-relative <= 1e-12 with
+the reference floored at 1e-4 RMS, density 1e-14, force and torque 1e-10 of
+the largest; FP32 -- velocity 1e-5, force 1e-4; FP16S -- velocity 5e-3,
+density 1e-3, force 5e-3 (FP16 storage of 256 (f - w) / w holds ~3 decimal
+digits of each deviation)."""
+import numpy as np
+import pytest
+
+from paper_2312_14172_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STEPS = (1, 2)
+U_FLOOR = 1e-4
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_14172_amd import hlbm
+    hlbm.lib()
+    return hlbm
+
+
+def _state(name, seed):
+    wl = W.get(name)
+    rng = np.random.default_rng(seed)
+    parts = wl.particles.copy()
+    parts["vel"] = rng.normal(0.0, 2e-3, (len(parts), 3))
+    parts["omega"] = rng.normal(0.0, 2e-4, (len(parts), 3))
+    rho, u = W.smooth_fields(wl.n, seed, rho_amp=2e-3, u_amp=1e-2)
+    return wl, parts, rho, u
+
+
+_ORACLE = {}
+
+
+def _oracle(oracle_mod, name, seed):
+    key = (name, seed)
+    if key not in _ORACLE:
+        wl, parts, rho, u = _state(name, seed)
+        _log(f"oracle: {name} {sum(STEPS)} steps")
+        orc = oracle_mod.Oracle(wl.n, wl.bc, wl.tau, gravity=wl.gravity)
+        P = orc.to_parts(parts)
+        f = orc.equilibrium(rho, u)
+        del rho, u
+        F, T = orc.run(P, f, sum(STEPS))
+        r, uu, up, B = orc.fields(P, f)
+        del f
+        _ORACLE.clear()
+        _ORACLE[key] = dict(F=F, T=T, P=P, rho=r, u=uu, up=up, B=B)
+    return _ORACLE[key]
+
+
+def _gpu(H, name, seed, precision):
+    wl, parts, rho, u = _state(name, seed)
+    sim = H.Simulation(wl.n, wl.bc, wl.tau, precision, max_particles=len(parts), gravity=wl.gravity)
+    sim.set_fields(rho, u)
+    sim.set_particles(parts)
+    for s in STEPS:
+        sim.step(s)
+    F, T, st = sim.get_forces()
+    fl = sim.get_fields()
+    sim.close()
+    return F, T, st, fl
+
+
+def _l2rel(a, b, floor=0.0):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), floor * np.sqrt(b.size), 1e-300))
+
+
+CASES = [("spheres128", "fp64"), ("spheres128", "fp32"), ("mixed256", "fp64"), ("mixed256", "fp16s")]
+
+
+@pytest.mark.parametrize("name,precision", CASES)
+def test_full_size_matches_oracle(H, oracle_mod, name, precision):
+    ref = _oracle(oracle_mod, name, 5)
+    _log(f"gpu: {name} {precision} full size, steps {STEPS}")
+    F, T, st, fl = _gpu(H, name, 5, precision)
+    eu = _l2rel(fl["u"], ref["u"], U_FLOOR)
+    erho = float(np.max(np.abs(fl["rho"] - ref["rho"])))
+    sF, sT = np.max(np.abs(ref["F"])), np.max(np.abs(ref["T"]))
+    eF = float(np.max(np.abs(F - ref["F"])) / sF)
+    eT = float(np.max(np.abs(T - ref["T"])) / sT)
+    eB = float(np.max(np.abs(fl["B"] - ref["B"])))
+    _log(f"  L2rel(u) floored {eu:.3e}  max|drho| {erho:.3e}  F {eF:.3e}  T {eT:.3e}  max|dB| {eB:.3e}")
+    tol = {"fp64": (1e-12, 1e-14, 1e-10), "fp32": (1e-5, 1e-6, 1e-4), "fp16s": (5e-3, 1e-3, 5e-3)}[precision]
+    assert eu <= tol[0]
+    assert erho <= tol[1]
+    assert eF <= tol[2] and eT <= 10 * tol[2]
+    if precision == "fp64":
+        assert _l2rel(fl["u_phys"], ref["up"], U_FLOOR) <= 1e-12
+        assert eB <= 1e-12
+        np.testing.assert_allclose(st["pos"], ref["P"]["X"], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(st["quat"], ref["P"]["q"], rtol=0, atol=1e-12)
+    else:
+        # particle geometry is evaluated in FP32: B moves by the rounding of
+        # the offsets times the indicator's slope (pi / eps)
+        assert eB <= 1e-4

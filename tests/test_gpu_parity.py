@@ -134,6 +134,30 @@ def test_mixed_moving_particles_fp64_ragged_tiles(H, oracle_mod, seed):
     np.testing.assert_allclose(r["st"]["omega"], r["P"]["W"], rtol=0, atol=1e-13)
 
 
+def test_particles_crossing_tiles_and_periodic_boundary(H, oracle_mod):
+    """Fast particles that move by several cells: their coupling and binning
+    boxes shift across tile boundaries (and one wraps across the periodic x
+    boundary), so every box and tile list is rebuilt from the moving state;
+    60 steps in three calls against the oracle."""
+    n, bc = (70, 26, 30), (0, 0, 1)
+    parts = W.random_particles_small(n, 3, 4, r_eq=(2.5, 3.0), bc=bc)
+    parts["pos"][0] = (68.2, 7.3, 14.6)
+    parts["vel"] = [(0.05, 0.02, 0.0), (-0.03, 0.05, 0.004), (0.0, -0.05, -0.004)]
+    parts["omega"] = [(0.0, 0.0, 0.01), (0.008, 0.0, 0.0), (0.0, -0.01, 0.0)]
+    _log("gpu: particles crossing tiles, 60 steps")
+    r = _run_both(H, oracle_mod, n, bc, 0.8, parts, 60, split=(1, 29, 30))
+    moved = np.abs(r["st"]["pos"] - parts["pos"])
+    moved = np.minimum(moved, np.array(n) - moved)
+    _log(f"  moved {np.round(moved.max(1), 2)}  L2rel(u)={_l2rel(r['fl']['u'], r['u'], U_FLOOR):.3e}")
+    assert moved.max() > 1.0
+    assert _l2rel(r["fl"]["u"], r["u"], U_FLOOR) <= 1e-12
+    assert np.max(np.abs(r["fl"]["rho"] - r["rho"])) <= 1e-14
+    np.testing.assert_allclose(r["fl"]["B"], r["B"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(r["F"], r["Fo"], rtol=0, atol=1e-10 * np.max(np.abs(r["Fo"])))
+    np.testing.assert_allclose(r["T"], r["To"], rtol=0, atol=1e-9 * np.max(np.abs(r["To"])))
+    np.testing.assert_allclose(r["st"]["pos"], r["P"]["X"], rtol=0, atol=1e-12)
+
+
 def test_fields_before_any_step_and_zero_steps(H, oracle_mod):
     wl = W.single_sphere()
     sim = H.Simulation(wl.n, wl.bc, wl.tau, "fp64", max_particles=1, gravity=wl.gravity)
