@@ -457,9 +457,12 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
     if (ctx->n > 0) {
       // momentum exchange on the state of time t, then Newton-Euler -> t+1 and
       // binning of the updated particles into the other tile-list buffer
-      HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, ctx->partial, s));
-      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, ctx->partial, ctx->tcnt[nxt], ctx->tlist[nxt],
-                             ctx->status, s));
+      // (slabs of 2 z-layers per workgroup for few particles, 4 for many:
+      // enough workgroups to fill the chip, few enough to amortise each)
+      const int layers = ctx->n >= 1000 ? 4 : 2;
+      HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers, ctx->partial, s));
+      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, layers, ctx->partial, ctx->tcnt[nxt],
+                             ctx->tlist[nxt], ctx->status, s));
       int rc = refresh_tables(ctx);
       if (rc) return rc;
     }

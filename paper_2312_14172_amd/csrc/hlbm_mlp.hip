@@ -357,7 +357,7 @@ __global__ void k_sdf_samples(int shape, double p0, double p1, uint64_t seed, in
 // grid = (ceil(cap / TAB_CHUNK), n), one wave per chunk of TAB_CHUNK cells: the
 // chunk's shell cells are compacted in LDS and evaluated in 16-cell tiles.
 // ---------------------------------------------------------------------------
-constexpr int TAB_CHUNK = 256;
+constexpr int TAB_CHUNK = 128;
 
 __global__ __launch_bounds__(64) void k_mlp_table(Lattice L, const DevParticle *__restrict__ parts,
                                                   const float *th_cube, const __bf16 *pk_cube, const float *th_sph,

@@ -137,14 +137,13 @@ __device__ inline void cross_sub(const double *a, const double *b, double *o) {
 // (directions whose neighbour lies past a wall are skipped).  The force on the
 // particle is -sum F_h, the torque -sum (x_b - X) x F_h.
 //
-// One workgroup per (particle, slab of MEA_LAYERS z-layers of its bounding
+// One workgroup per (particle, slab of a few z-layers of its bounding
 // box).  The slab's cells are classified 256 at a time; the inside ones are
 // compacted into an LDS queue (in cell order, which keeps the x-runs of a
 // convex body contiguous for the loads) and drained 256 at a time, so the 36
 // population loads and the FP64 sums run on full wavefronts.  Each thread
 // accumulates its cells in queue order; the slab's sum is reduced with a fixed
 // wavefront-shuffle tree in FP64 and written as one record.
-constexpr int MEA_LAYERS = 4;
 
 // A cell of the slab, as box-relative coordinates packed in one int
 // (x | y << 8 | z << 16, each < 256), its wrapped lattice coordinates and its
@@ -280,10 +279,10 @@ __device__ inline void advance_particle(const Lattice &L, DevParticle &p, const 
   }
 }
 
-// Number of MEA_LAYERS-slabs of a momentum-exchange box (at least one: an empty
-// box still writes a zero record).
-__device__ inline int mea_slabs(int lo2, int hi2) {
-  return hi2 < lo2 ? 1 : (hi2 - lo2 + MEA_LAYERS) / MEA_LAYERS;
+// Number of slabs of `layers` z-layers of a momentum-exchange box (at least
+// one: an empty box still writes a zero record).
+__device__ inline int mea_slabs(int lo2, int hi2, int layers) {
+  return hi2 < lo2 ? 1 : (hi2 - lo2 + layers) / layers;
 }
 
 // Momentum exchange of one slab: workgroup (order[x], slab) reduces the slab's
@@ -294,7 +293,7 @@ __device__ inline int mea_slabs(int lo2, int hi2) {
 template <class ST, bool O32>
 __global__ __launch_bounds__(256) void k_mea(Lattice L, const typename ST::S *__restrict__ A,
                                              const DevParticle *__restrict__ parts, const int *__restrict__ order,
-                                             int lmax, double *__restrict__ partial) {
+                                             int lmax, int layers, double *__restrict__ partial) {
   __shared__ int queue[512];
   __shared__ int wcnt[4];
   __shared__ double red[4][6];
@@ -304,12 +303,12 @@ __global__ __launch_bounds__(256) void k_mea(Lattice L, const typename ST::S *__
   MeaBox g;
   int hi[3];
   cell_box(L, sp.X, sp.rc + 1e-9, g.lo, hi);
-  const int nslab = mea_slabs(g.lo[2], hi[2]);
+  const int nslab = mea_slabs(g.lo[2], hi[2], layers);
   if (slab >= nslab) return;   // uniform per workgroup
-  g.lo[2] += slab * MEA_LAYERS;
+  g.lo[2] += slab * layers;
   g.sx = hi[0] - g.lo[0] + 1;
   g.sy = hi[1] - g.lo[1] + 1;
-  g.nl = min(MEA_LAYERS, hi[2] - g.lo[2] + 1);
+  g.nl = min(layers, hi[2] - g.lo[2] + 1);
   for (int k = 0; k < 3; ++k) g.X[k] = sp.X[k];
   const int shape = sp.shape;
   const double p0 = sp.prm[0], p1 = sp.prm[1];
@@ -397,8 +396,8 @@ __global__ __launch_bounds__(256) void k_mea(Lattice L, const typename ST::S *__
 // 64 partial sums are added in order), the equations of motion, then the
 // particle appended to the tile lists of its new coupling box.
 __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restrict__ parts, int lmax,
-                                                const double *__restrict__ partial, int *tcnt, int *tlist,
-                                                int *status) {
+                                                int layers, const double *__restrict__ partial, int *tcnt,
+                                                int *tlist, int *status) {
   __shared__ double red[64][6];
   __shared__ int ts[3][MAX_AXIS_TILES];
   __shared__ int tn[3];
@@ -406,7 +405,7 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
   const int t = threadIdx.x;
   int lo[3], hi[3];
   cell_box(L, parts[pid].X, parts[pid].rc + 1e-9, lo, hi);
-  const int nrec = mea_slabs(lo[2], hi[2]);
+  const int nrec = mea_slabs(lo[2], hi[2], layers);
   const double *src = partial + (size_t)pid * lmax * 6;
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int r = t; r < nrec; r += 64)
@@ -475,22 +474,22 @@ hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int cap
 }
 
 hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevParticle *parts, const int *order, int n,
-                      int lmax, double *partial, hipStream_t s) {
+                      int lmax, int layers, double *partial, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const dim3 grid(n, (lmax + MEA_LAYERS - 1) / MEA_LAYERS);
+  const dim3 grid(n, (lmax + layers - 1) / layers);
   HLBM_DISPATCH(prec, {
     if ((unsigned long long)L.N * sizeof(typename ST::S) < (1ull << 32))
-      hipLaunchKernelGGL((k_mea<ST, true>), grid, dim3(256), 0, s, L, (const typename ST::S *)A, parts, order, lmax, partial);
+      hipLaunchKernelGGL((k_mea<ST, true>), grid, dim3(256), 0, s, L, (const typename ST::S *)A, parts, order, lmax, layers, partial);
     else
-      hipLaunchKernelGGL((k_mea<ST, false>), grid, dim3(256), 0, s, L, (const typename ST::S *)A, parts, order, lmax, partial);
+      hipLaunchKernelGGL((k_mea<ST, false>), grid, dim3(256), 0, s, L, (const typename ST::S *)A, parts, order, lmax, layers, partial);
   });
   return hipGetLastError();
 }
 
-hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, const double *partial,
+hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, const double *partial,
                           int *tcnt, int *tlist, int *status, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eom_bin, dim3(n), dim3(64), 0, s, L, parts, lmax, partial, tcnt, tlist, status);
+  hipLaunchKernelGGL(k_eom_bin, dim3(n), dim3(64), 0, s, L, parts, lmax, layers, partial, tcnt, tlist, status);
   return hipGetLastError();
 }
 
