@@ -178,10 +178,12 @@ int hlbm_profile_end(hlbm_ctx *ctx, double *collide_ms, int64_t *launches);
  * 3 -> 64 -> 64 -> 64 -> 1 with SiLU activations maps a body-frame point
  * divided by the circumradius R_c to d_s / R_c.  BF16 matrix-core products
  * with FP32 accumulation; FP32 master parameters trained with Adam.  When a
- * family is in HLBM_INDICATOR_LEARNED mode, every step evaluates the network
- * at the cells of each such particle's coupling box (a per-particle distance
- * table) and both the indicator B(d_s) and the inside test d_s <= 0 of the
- * momentum exchange use it.  Requires cfg.learned = 1.
+ * family is in HLBM_INDICATOR_LEARNED mode, every step fills a per-particle
+ * distance table over each such particle's coupling box: the network is
+ * queried on the shell r_in - eps/2 <= |x - X| <= R_c + eps/2 (r_in the
+ * inscribed radius), cells nearer the centre count as inside (B = 1), cells
+ * farther as outside (B = 0); both the indicator B(d_s) and the inside test
+ * d_s <= 0 of the momentum exchange read the table.  Requires cfg.learned = 1.
  *
  * Parameters are one flat float vector of HLBM_MLP_NPARAM entries in the
  * order W1 (64x3, row-major), b1 (64), W2 (64x64), b2, W3 (64x64), b3,
