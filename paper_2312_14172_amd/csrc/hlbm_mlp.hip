@@ -415,6 +415,10 @@ __global__ __launch_bounds__(64) void k_mlp_table(Lattice L, const DevParticle *
   // evaluate 64 shell cells per pass as four 16-cell tiles
   for (int t0 = 0; t0 < nq; t0 += 64) {
     for (int q = 0; q < 4; ++q) {
+      // the per-lane parameters are re-read (L1) for every tile instead of
+      // being hoisted out of the loop: that would hold ~110 more registers and
+      // halve the waves per SIMD that hide the MFMA and SiLU latencies
+      __asm__ volatile("" ::: "memory");
       const int k = t0 + q * 16 + li;
       const bool ok = k < nq;
       const float x0 = ok ? qx[0][k] : 0.f, x1 = ok ? qx[1][k] : 0.f, x2 = ok ? qx[2][k] : 0.f;

@@ -391,14 +391,13 @@ __global__ __launch_bounds__(256) void k_mea(Lattice L, const typename ST::S *__
   if (t < 6) partial[((size_t)pid * lmax + slab) * 6 + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
 }
 
-// One 64-thread workgroup per particle: the slab records of k_mea loaded in
-// parallel and summed in slab order (thread t sums slabs t, t + 64, ...; the
-// 64 partial sums are added in order), the equations of motion, then the
-// particle appended to the tile lists of its new coupling box.
+// One 64-thread workgroup per particle: the slab records of k_mea summed in a
+// fixed order (thread t takes slabs t, t + 64, ..., then a fixed wavefront
+// butterfly), the equations of motion, then the particle appended to the tile
+// lists of its new coupling box.
 __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restrict__ parts, int lmax,
                                                 int layers, const double *__restrict__ partial, int *tcnt,
                                                 int *tlist, int *status) {
-  __shared__ double red[64][6];
   __shared__ int ts[3][MAX_AXIS_TILES];
   __shared__ int tn[3];
   const int pid = blockIdx.x;
@@ -410,14 +409,10 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int r = t; r < nrec; r += 64)
     for (int k = 0; k < 6; ++k) acc[k] += src[r * 6 + k];
-  for (int k = 0; k < 6; ++k) red[t][k] = acc[k];
-  __syncthreads();
+  for (int k = 0; k < 6; ++k) acc[k] = wave_sum(acc[k]);
   if (t == 0) {
-    double Fs[6] = {0, 0, 0, 0, 0, 0};
-    for (int l = 0; l < 64; ++l)
-      for (int k = 0; k < 6; ++k) Fs[k] += red[l][k];
     DevParticle p = parts[pid];
-    advance_particle(L, p, Fs, status);
+    advance_particle(L, p, acc, status);
     parts[pid] = p;
     tn[0] = axis_tiles(p.lo[0], p.hi[0], L.nx, !L.bc[0], TX, ts[0]);
     tn[1] = axis_tiles(p.lo[1], p.hi[1], L.ny, !L.bc[1], TY, ts[1]);
