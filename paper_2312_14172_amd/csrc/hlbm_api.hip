@@ -117,7 +117,7 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
       y.theta[f] = off; off += align_up(MLP_PARTIAL * sizeof(float));
       y.mom1[f] = off; off += align_up(MLP_PARTIAL * sizeof(float));
       y.mom2[f] = off; off += align_up(MLP_PARTIAL * sizeof(float));
-      y.packed[f] = off; off += align_up(MLP_PACKED * 2);
+      y.packed[f] = off; off += align_up(MLP_PACKED_BYTES);
     }
     y.gpart = off; off += align_up((size_t)MLP_MAX_BLOCKS * MLP_PARTIAL * sizeof(float));
     y.gout = off; off += align_up(MLP_PARTIAL * sizeof(float));

@@ -18,6 +18,8 @@ constexpr int MLP_OFF_B4 = 8640;
 constexpr int MLP_NPARAM = 8641;
 constexpr int MLP_PARTIAL = MLP_NPARAM + 1;  // gradient + squared-error sum
 constexpr int MLP_PACKED = 4 * 4096;         // bf16 entries of the four packed 64x64 operands
+constexpr int MLP_LANE_F4 = 28;              // float4 forward parameters per lane group (after them)
+constexpr int MLP_PACKED_BYTES = MLP_PACKED * 2 + 4 * MLP_LANE_F4 * 16;
 constexpr int MLP_MAX_BLOCKS = 512;          // workgroups of one gradient launch
 
 hipError_t mlp_pack(const float *theta, __bf16 *packed, hipStream_t s);

@@ -22,9 +22,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline int kappa(int c, int g, int e) { return 32 * c + 4 * g + (e & 3) + 16 * (e >> 2); }
 
-__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware reciprocal (1 ulp).
+__device__ inline float sigm_f(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ inline float silu_f(float z) { return z * sigm_f(z); }
 __device__ inline float dsilu_f(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigm_f(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
@@ -46,9 +48,27 @@ __device__ inline void pack_b(const float *v, bf16x8 *b) {
 // ---------------------------------------------------------------------------
 // wf[L][(ot*2 + c)*64 + lane][e] = W_L[16 ot + lane%16][kappa(c, lane/16, e)]  (forward, A = W)
 // wb[L][(kt*2 + c)*64 + lane][e] = W_L[kappa(c, lane/16, e)][16 kt + lane%16]  (backward, A = W^T)
+// followed by the FP32 parameters a lane of group g = lane/16 needs in the
+// forward pass, as MLP_LANE_F4 float4 per group (features f = 16 ot + 4 g + j):
+//   [4 ot + j] = (W1[f][0..2], b1[f]),  [16 + ot] = b2[f(j = 0..3)],
+//   [20 + ot] = b3[..],  [24 + ot] = W4[..].
 __global__ void k_mlp_pack(const float *__restrict__ theta, __bf16 *__restrict__ packed) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. 4 * 4096
-  if (t >= 4 * 4096) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. 4 * 4096 + 4 * MLP_LANE_F4 * 4
+  if (t >= 4 * 4096) {
+    const int r = t - 4 * 4096;
+    if (r >= 4 * MLP_LANE_F4 * 4) return;
+    const int comp = r % 4, slot = r / 4, g = slot / MLP_LANE_F4, k = slot % MLP_LANE_F4;
+    float v;
+    if (k < 16) {
+      const int f = 16 * (k / 4) + 4 * g + k % 4;
+      v = comp < 3 ? theta[MLP_OFF_W1 + 3 * f + comp] : theta[MLP_OFF_B1 + f];
+    } else {
+      const int ot = (k - 16) % 4, f = 16 * ot + 4 * g + comp;
+      v = theta[(k < 20 ? MLP_OFF_B2 : (k < 24 ? MLP_OFF_B3 : MLP_OFF_W4)) + f];
+    }
+    ((float *)(packed + MLP_PACKED))[r] = v;
+    return;
+  }
   const int which = t / 4096;  // 0: wf2, 1: wf3, 2: wb2, 3: wb3
   const int r = t % 4096;
   const int e = r % 8, lane = (r / 8) % 64, c = (r / 512) % 2, tile = r / 1024;
@@ -64,11 +84,13 @@ __global__ void k_mlp_pack(const float *__restrict__ theta, __bf16 *__restrict__
 struct MlpArgs {
   const float *theta;
   const bf16x8 *wf2, *wf3, *wb2, *wb3;
+  const float4 *lane;  // per-lane-group forward parameters
 };
 
 __device__ inline MlpArgs mlp_args(const float *theta, const __bf16 *packed) {
   MlpArgs a;
   a.theta = theta;
+  a.lane = (const float4 *)(packed + MLP_PACKED);
   a.wf2 = (const bf16x8 *)(packed);
   a.wf3 = (const bf16x8 *)(packed + 4096);
   a.wb2 = (const bf16x8 *)(packed + 2 * 4096);
@@ -82,15 +104,14 @@ __device__ inline MlpArgs mlp_args(const float *theta, const __bf16 *packed) {
 __device__ inline void mlp_forward_tile(const MlpArgs &A, float x0, float x1, float x2, float *z1, float *z2,
                                         float *z3, float &y) {
   const int l = threadIdx.x & 63, g = l >> 4;
-  const float *th = A.theta;
+  const float4 *P = A.lane + g * MLP_LANE_F4;
   float h[16];
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int f = 16 * ot + 4 * g + j;
-      const float z = th[MLP_OFF_B1 + f] + th[MLP_OFF_W1 + 3 * f] * x0 + th[MLP_OFF_W1 + 3 * f + 1] * x1 +
-                      th[MLP_OFF_W1 + 3 * f + 2] * x2;
+      const float4 w = P[4 * ot + j];
+      const float z = w.w + w.x * x0 + w.y * x1 + w.z * x2;
       z1[ot * 4 + j] = z;
       h[ot * 4 + j] = silu_f(z);
     }
@@ -101,8 +122,11 @@ __device__ inline void mlp_forward_tile(const MlpArgs &A, float x0, float x1, fl
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     acc = mfma(A.wf2[(ot * 2 + 0) * 64 + l], b[0], acc);
     acc = mfma(A.wf2[(ot * 2 + 1) * 64 + l], b[1], acc);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) z2[ot * 4 + j] = acc[j] + th[MLP_OFF_B2 + 16 * ot + 4 * g + j];
+    const float4 bb = P[16 + ot];
+    z2[ot * 4 + 0] = acc[0] + bb.x;
+    z2[ot * 4 + 1] = acc[1] + bb.y;
+    z2[ot * 4 + 2] = acc[2] + bb.z;
+    z2[ot * 4 + 3] = acc[3] + bb.w;
   }
 #pragma unroll
   for (int k = 0; k < 16; ++k) h[k] = silu_f(z2[k]);
@@ -112,17 +136,22 @@ __device__ inline void mlp_forward_tile(const MlpArgs &A, float x0, float x1, fl
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     acc = mfma(A.wf3[(ot * 2 + 0) * 64 + l], b[0], acc);
     acc = mfma(A.wf3[(ot * 2 + 1) * 64 + l], b[1], acc);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) z3[ot * 4 + j] = acc[j] + th[MLP_OFF_B3 + 16 * ot + 4 * g + j];
+    const float4 bb = P[20 + ot];
+    z3[ot * 4 + 0] = acc[0] + bb.x;
+    z3[ot * 4 + 1] = acc[1] + bb.y;
+    z3[ot * 4 + 2] = acc[2] + bb.z;
+    z3[ot * 4 + 3] = acc[3] + bb.w;
   }
   float part = 0.f;
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) part += th[MLP_OFF_W4 + 16 * ot + 4 * g + j] * silu_f(z3[ot * 4 + j]);
+  for (int ot = 0; ot < 4; ++ot) {
+    const float4 w4 = P[24 + ot];
+    part += w4.x * silu_f(z3[ot * 4 + 0]) + w4.y * silu_f(z3[ot * 4 + 1]) + w4.z * silu_f(z3[ot * 4 + 2]) +
+            w4.w * silu_f(z3[ot * 4 + 3]);
+  }
   part += __shfl_xor(part, 16, 64);
   part += __shfl_xor(part, 32, 64);
-  y = part + th[MLP_OFF_B4];
+  y = part + A.theta[MLP_OFF_B4];
 }
 
 // ---------------------------------------------------------------------------
@@ -443,7 +472,7 @@ hipError_t launch_mlp_table(const Lattice &L, const DevParticle *parts, int n, c
 }
 
 hipError_t mlp_pack(const float *theta, __bf16 *packed, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_pack, dim3(4 * 4096 / 256), dim3(256), 0, s, theta, packed);
+  hipLaunchKernelGGL(k_mlp_pack, dim3((4 * 4096 + 4 * MLP_LANE_F4 * 4 + 255) / 256), dim3(256), 0, s, theta, packed);
   return hipGetLastError();
 }
 
