@@ -471,7 +471,9 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
     if (ctx->profiling) {
       while (ctx->events.size() < ctx->events_used + 2) {
         hipEvent_t e;
-        HIP_TRY(hipEventCreate(&e));
+        // timing-only events: no system-scope fence (no cache writeback and
+        // invalidation between the launches they bracket)
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         ctx->events.push_back(e);
       }
       HIP_TRY(hipEventRecord(ctx->events[ctx->events_used], s));
