@@ -78,20 +78,21 @@ struct DevParticle {
 };
 
 // Tiles touched by a cell range along one axis (wrapped on periodic axes),
-// in increasing cell order; returns the count (<= MAX_AXIS_TILES).
+// in increasing cell order; returns the count (<= MAX_AXIS_TILES).  Steps from
+// tile to tile (one division per tile, not per cell).
 __device__ inline int axis_tiles(int lo, int hi, int n, int periodic, int tsize, int *out) {
-  int cnt = 0, last = -1;
-  for (int c = lo; c <= hi; ++c) {
+  int cnt = 0;
+  int c = lo;
+  while (c <= hi) {
     int w = c;
     if (periodic) { w %= n; if (w < 0) w += n; }
-    if (w < 0 || w >= n) continue;
+    if (w < 0) { c = 0; continue; }
+    if (w >= n) break;
     const int t = w / tsize;
-    if (t != last) {
-      bool seen = false;
-      for (int k = 0; k < cnt; ++k) seen |= (out[k] == t);
-      if (!seen && cnt < MAX_AXIS_TILES) out[cnt++] = t;
-      last = t;
-    }
+    bool seen = false;
+    for (int k = 0; k < cnt; ++k) seen |= (out[k] == t);
+    if (!seen && cnt < MAX_AXIS_TILES) out[cnt++] = t;
+    c += min((t + 1) * tsize, n) - w;  // first cell of the next tile
   }
   return cnt;
 }

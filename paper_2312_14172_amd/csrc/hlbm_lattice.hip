@@ -253,8 +253,15 @@ __device__ inline void tile_coupling(const Lattice &L, const TileCands<G> &tc, i
       for (int py = 0; py < nyp; ++py)
         for (int px = 0; px < nxp; ++px) {
           const int sx = bx[px] - ax[px] + 1, sy = by[py] - ay[py] + 1, sz = bz[pz] - az[pz] + 1;
+          // k -> (x, y, z) of the piece without integer division: k < 1024 and
+          // sx, sy <= 64, so floor((k + 1/2) / s) in FP32 is exact (the
+          // rounding error stays far below 1/(2 s))
+          const float isx = 1.0f / (float)sx, isxy = 1.0f / (float)(sx * sy);
           for (int k = threadIdx.x; k < sx * sy * sz; k += blockDim.x) {
-            const int lx = ax[px] + k % sx, ly = ay[py] + (k / sx) % sy, lz = az[pz] + k / (sx * sy);
+            const int kz = (int)(((float)k + 0.5f) * isxy);
+            const int kxy = k - kz * sx * sy;
+            const int ky = (int)(((float)kxy + 0.5f) * isx);
+            const int lx = ax[px] + kxy - ky * sx, ly = ay[py] + ky, lz = az[pz] + kz;
             G d0, d1, d2;
             const G Bp = cell_indicator<G>(L, c, tx * TX + lx, ty * TY + ly, tz * TZ + lz, d0, d1, d2, he, eps,
                                            inv_eps);

@@ -291,7 +291,7 @@ __device__ inline int mea_slabs(int lo2, int hi2, int layers) {
 // (x, row)), the inside cells are compacted into the LDS queue, and full
 // queues of 256 cells are drained by all threads at once.
 template <class ST, bool O32>
-__global__ __launch_bounds__(256) void k_mea(Lattice L, const typename ST::S *__restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST::kind == 2 ? 4 : 3))) void k_mea(Lattice L, const typename ST::S *__restrict__ A,
                                              const DevParticle *__restrict__ parts, const int *__restrict__ order,
                                              int lmax, int layers, double *__restrict__ partial) {
   __shared__ int queue[512];
@@ -402,12 +402,21 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
   __shared__ int tn[3];
   const int pid = blockIdx.x;
   const int t = threadIdx.x;
+  // the slab records are loaded before their count is known (every slot up
+  // to the largest count exists), so the loads overlap the box computation
+  const double *src = partial + (size_t)pid * lmax * 6;
+  const int nmax = (lmax + layers - 1) / layers;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double first[6];
+  const bool have = t < nmax;
+  if (have)
+    for (int k = 0; k < 6; ++k) first[k] = src[t * 6 + k];
   int lo[3], hi[3];
   cell_box(L, parts[pid].X, parts[pid].rc + 1e-9, lo, hi);
   const int nrec = mea_slabs(lo[2], hi[2], layers);
-  const double *src = partial + (size_t)pid * lmax * 6;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int r = t; r < nrec; r += 64)
+  if (have && t < nrec)
+    for (int k = 0; k < 6; ++k) acc[k] = first[k];
+  for (int r = t + 64; r < nrec; r += 64)
     for (int k = 0; k < 6; ++k) acc[k] += src[r * 6 + k];
   for (int k = 0; k < 6; ++k) acc[k] = wave_sum(acc[k]);
   if (t == 0) {
