@@ -179,10 +179,8 @@ __device__ inline G axis_offset(int cell, int xi, G off, int n, int periodic) {
 // Per-tile coupling fields in LDS: for every cell of the tile
 //   S0 = sum_p B_p,  S1 = sum_p B_p u_p(x)      (Sec. 3.2; overlap reading:
 //   B = min(1, S0), u_s = S1 / S0).
-// The tile's particles are processed one after the other in index order; for
-// each, the cells of its coupling box inside the tile are spread densely over
-// the workgroup, so only those cells are evaluated and every LDS entry has a
-// single writer per pass (fixed summation order).
+// The tile's particles are processed one after the other in index order; each
+// LDS entry is written by one wavefront only (fixed summation order).
 template <typename G>
 struct TileFields {
   G S0[TZ * TY * TX];
@@ -227,55 +225,60 @@ __device__ inline G cell_indicator(const Lattice &L, const Cand<G> &c, int x, in
   return indicator<G>(sdf_for_indicator<G>(c.shape, c.p0, c.p1, c.ia2, c.ib2, b0, b1, b2, he), eps, inv_eps);
 }
 
-// Fills tf for tile (tx, ty, tz); ends with a barrier.  Skips everything when
-// the tile has no particles (tf is then not touched).
+// Fills tf for tile (tx, ty, tz).  Each wavefront fills the y-row of the tile
+// it later collides (cells x = lane, y = wave, all z), so no barrier is
+// needed: for each particle in index order, the particle's coupling-box cells
+// in that row are spread densely over the wavefront's lanes.  Skips
+// everything when the tile has no particles (tf is then not touched).
 template <typename G>
 __device__ inline void tile_coupling(const Lattice &L, const TileCands<G> &tc, int tx, int ty, int tz,
                                      TileFields<G> &tf) {
   const int nc = tc.n;
   if (nc == 0) return;
-  const int ncell = TZ * TY * TX;
-  for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+  const int w = wave_id(), lane = lane_id();
+#pragma unroll
+  for (int z = 0; z < TZ; ++z) {
+    const int k = lane + TX * (w + TY * z);
     tf.S0[k] = G(0);
     tf.S1[0][k] = tf.S1[1][k] = tf.S1[2][k] = G(0);
   }
-  __syncthreads();
   const G he = G(0.5) * (G)L.eps;
   const G eps = (G)L.eps;
   const G inv_eps = (G)(1.0 / L.eps);
   for (int ci = 0; ci < nc; ++ci) {
     const Cand<G> &c = tc.c[ci];
-    int ax[2], bx[2], ay[2], by[2], az[2], bz[2];
-    const int nxp = axis_pieces(c.lo[0], c.hi[0], tx * TX, TX, L.nx, !L.bc[0], ax, bx);
+    int ay[2], by[2];
     const int nyp = axis_pieces(c.lo[1], c.hi[1], ty * TY, TY, L.ny, !L.bc[1], ay, by);
+    bool row = false;
+    for (int py = 0; py < nyp; ++py) row |= (w >= ay[py] && w <= by[py]);
+    if (!row) continue;  // uniform per wavefront
+    int ax[2], bx[2], az[2], bz[2];
+    const int nxp = axis_pieces(c.lo[0], c.hi[0], tx * TX, TX, L.nx, !L.bc[0], ax, bx);
     const int nzp = axis_pieces(c.lo[2], c.hi[2], tz * TZ, TZ, L.nz, !L.bc[2], az, bz);
     for (int pz = 0; pz < nzp; ++pz)
-      for (int py = 0; py < nyp; ++py)
-        for (int px = 0; px < nxp; ++px) {
-          const int sx = bx[px] - ax[px] + 1, sy = by[py] - ay[py] + 1, sz = bz[pz] - az[pz] + 1;
-          // k -> (x, y, z) of the piece without integer division: k < 1024 and
-          // sx, sy <= 64, so floor((k + 1/2) / s) in FP32 is exact (the
-          // rounding error stays far below 1/(2 s))
-          const float isx = 1.0f / (float)sx, isxy = 1.0f / (float)(sx * sy);
-          for (int k = threadIdx.x; k < sx * sy * sz; k += blockDim.x) {
-            const int kz = (int)(((float)k + 0.5f) * isxy);
-            const int kxy = k - kz * sx * sy;
-            const int ky = (int)(((float)kxy + 0.5f) * isx);
-            const int lx = ax[px] + kxy - ky * sx, ly = ay[py] + ky, lz = az[pz] + kz;
-            G d0, d1, d2;
-            const G Bp = cell_indicator<G>(L, c, tx * TX + lx, ty * TY + ly, tz * TZ + lz, d0, d1, d2, he, eps,
-                                           inv_eps);
-            if (Bp > G(0)) {
-              const int idx = lx + TX * (ly + TY * lz);
-              tf.S0[idx] += Bp;
-              tf.S1[0][idx] += Bp * (c.U[0] + c.W[1] * d2 - c.W[2] * d1);
-              tf.S1[1][idx] += Bp * (c.U[1] + c.W[2] * d0 - c.W[0] * d2);
-              tf.S1[2][idx] += Bp * (c.U[2] + c.W[0] * d1 - c.W[1] * d0);
-            }
+      for (int px = 0; px < nxp; ++px) {
+        const int sx = bx[px] - ax[px] + 1, sz = bz[pz] - az[pz] + 1;
+        // k -> (x, z) of the piece without integer division: k < 256 and
+        // sx <= 64, so floor((k + 1/2) / sx) in FP32 is exact
+        const float isx = 1.0f / (float)sx;
+        for (int k = lane; k < sx * sz; k += 64) {
+          const int kz = (int)(((float)k + 0.5f) * isx);
+          const int lx = ax[px] + k - kz * sx, lz = az[pz] + kz;
+          G d0, d1, d2;
+          const G Bp = cell_indicator<G>(L, c, tx * TX + lx, ty * TY + w, tz * TZ + lz, d0, d1, d2, he, eps,
+                                         inv_eps);
+          if (Bp > G(0)) {
+            const int idx = lx + TX * (w + TY * lz);
+            tf.S0[idx] += Bp;
+            tf.S1[0][idx] += Bp * (c.U[0] + c.W[1] * d2 - c.W[2] * d1);
+            tf.S1[1][idx] += Bp * (c.U[1] + c.W[2] * d0 - c.W[0] * d2);
+            tf.S1[2][idx] += Bp * (c.U[2] + c.W[0] * d1 - c.W[1] * d0);
           }
         }
-    __syncthreads();
+      }
   }
+  // the row's LDS writes precede the wavefront's own reads in the cell loop
+  __builtin_amdgcn_wave_barrier();
 }
 
 // Fused collide + stream with the exact-difference source (one workgroup per
@@ -310,6 +313,14 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
   using G = typename ST::G;
   __shared__ TileCands<G> tc;
   __shared__ TileFields<G> tf;
+  const T K = ST::K();
+  const T invK = (T)1 / K;
+  const T omega = (T)L.omega;
+  const T one_m_omega = (T)1 - omega;
+  const T afx = (T)L.af[0], afy = (T)L.af[1], afz = (T)L.af[2];
+  const bool has_af = (L.af[0] != 0.0) || (L.af[1] != 0.0) || (L.af[2] != 0.0);
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+
   const int tile = xcd_tile(blockIdx.x, L.ntiles);
   const int tx = tile % L.ntx;
   const int ty = (tile / L.ntx) % L.nty;
@@ -319,14 +330,6 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
   // the other tile-list buffer is refilled by the next step's binning
   if (threadIdx.x == 0 && tcnt_clear) tcnt_clear[tile] = 0;
   tile_coupling<G>(L, tc, tx, ty, tz, tf);
-
-  const T K = ST::K();
-  const T invK = (T)1 / K;
-  const T omega = (T)L.omega;
-  const T one_m_omega = (T)1 - omega;
-  const T afx = (T)L.af[0], afy = (T)L.af[1], afz = (T)L.af[2];
-  const bool has_af = (L.af[0] != 0.0) || (L.af[1] != 0.0) || (L.af[2] != 0.0);
-  const int nx = L.nx, ny = L.ny, nz = L.nz;
 
   for (int zz = 0; zz < TZ; ++zz) {
     CellPos cp;
@@ -425,7 +428,8 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         typename ST::S *plane = Bo + (long long)i * L.N;
-        plane[(unsigned)cell] = ST::enc(out[i]);
+        // streamed out: nothing in this step reads it back
+        __builtin_nontemporal_store(ST::enc(out[i]), &plane[(unsigned)cell]);
       }
     }
   }
