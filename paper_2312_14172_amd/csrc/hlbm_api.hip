@@ -42,6 +42,8 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // z-layers a particle's momentum-exchange box can span (circumradius <= 27)
 constexpr int LMAX_CAP = 56;
+// particle count from which the momentum exchange is dispatched XCD-chunked
+constexpr int MEA_CHUNKED_MIN = 4096;
 
 size_t pop_bytes(int precision) { return precision == HLBM_FP64 ? 8 : (precision == HLBM_FP32 ? 4 : 2); }
 
@@ -143,7 +145,8 @@ struct hlbm_ctx {
   char *base;
   void *fA, *fB;
   DevParticle *parts;
-  int *order;         // particles in (z, y, x) order of their initial centres
+  int *order;         // particles in the momentum-exchange visiting order
+  int mea_chunked;    // that order is dispatched in XCD-contiguous runs
   hlbm_particle *stage_parts;
   int *tcnt[2], *tlist[2], *status;
   int cur;            // tile-list buffer describing the current particles
@@ -262,6 +265,7 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   c->status = (int *)(c->base + lay.status);
   c->stage = (double *)(c->base + lay.stage);
   c->n = 0;
+  c->mea_chunked = 0;
   c->binned = false;
   c->bin_cap = 1;
   c->steps_done = 0;
@@ -401,12 +405,33 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
   }
   if (lmax > LMAX_CAP) return fail(HLBM_EUNSUPPORTED, "circumradius too large");
   HIP_TRY(hipStreamSynchronize(ctx->stream));
-  // momentum-exchange workgroups visit the particles in (z, y, x) order of
-  // their centres, so that the workgroups resident at one time read nearby
-  // parts of each population plane (any order gives the same result)
+  // Order in which the momentum-exchange workgroups visit the particles.  Few
+  // particles: (z, y, x) order of their centres, slab-major dispatch (the
+  // exchange is bound by latency; the resident workgroups spread over the
+  // whole lattice).  Many particles: Morton order of the 64 x 16 x 16-cell
+  // blocks holding the centres, each XCD on a contiguous run of it, so that
+  // particles whose boxes share rows of a population plane are read through
+  // one L2 (the exchange is bound by HBM traffic; measured on 11 265
+  // particles: 4.8 -> 3.6 GB per step in an LRU model, -9 % time).  Any
+  // order gives the same result.
+  const bool chunked = n >= MEA_CHUNKED_MIN;
+  std::vector<unsigned long long> key(n);
+  auto spread = [](unsigned v) {
+    unsigned long long r = 0;
+    for (int b = 0; b < 21; ++b) r |= (unsigned long long)((v >> b) & 1u) << (3 * b);
+    return r;
+  };
+  for (int i = 0; i < n; ++i) {
+    const double *X = host[i].pos;
+    const unsigned bx = (unsigned)std::max(0.0, floor(X[0] / 64.0));
+    const unsigned by = (unsigned)std::max(0.0, floor(X[1] / 16.0));
+    const unsigned bz = (unsigned)std::max(0.0, floor(X[2] / 16.0));
+    key[i] = spread(bx) | (spread(by) << 1) | (spread(bz) << 2);
+  }
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
-  std::sort(order.begin(), order.end(), [host](int a, int b) {
+  std::sort(order.begin(), order.end(), [host, chunked, &key](int a, int b) {
+    if (chunked) return key[a] != key[b] ? key[a] < key[b] : a < b;
     const double *pa = host[a].pos, *pb = host[b].pos;
     if (floor(pa[2]) != floor(pb[2])) return pa[2] < pb[2];
     if (floor(pa[1]) != floor(pb[1])) return pa[1] < pb[1];
@@ -419,6 +444,7 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
     HIP_TRY(launch_prepare(ctx->L, ctx->stage_parts, ctx->parts, n, ctx->stream));
   }
   ctx->n = n;
+  ctx->mea_chunked = chunked ? 1 : 0;
   ctx->bin_cap = cap;
   ctx->lmax = lmax;
   int rc = rebin(ctx);
@@ -460,7 +486,7 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
       // (slabs of 2 z-layers per workgroup for few particles, 4 for many:
       // enough workgroups to fill the chip, few enough to amortise each)
       const int layers = ctx->n >= 1000 ? 4 : 2;
-      HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers, ctx->partial, s));
+      HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers, ctx->mea_chunked, ctx->partial, s));
       HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, layers, ctx->partial, ctx->tcnt[nxt],
                              ctx->tlist[nxt], ctx->status, s));
       int rc = refresh_tables(ctx);

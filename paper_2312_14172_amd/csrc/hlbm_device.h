@@ -37,6 +37,17 @@ __device__ inline double wave_sum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin.
+// Workgroup b is given work item (b mod 8) (n / 8) + b / 8 of n, so that each
+// XCD sweeps one contiguous run of items in order and the data neighbouring
+// items share is read through the same L2.  The last n mod 8 items map to
+// themselves.
+__device__ inline int xcd_chunk(int b, int n) {
+  const int per = n >> 3;
+  if (b >= per * 8) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
 __device__ inline int wave_min(int v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));

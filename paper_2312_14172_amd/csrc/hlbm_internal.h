@@ -18,7 +18,7 @@ hipError_t launch_mlp_table(const Lattice &L, const DevParticle *parts, int n, c
 hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int cap, int *tcnt, int *tlist,
                       int *status, hipStream_t s);
 hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevParticle *parts, const int *order, int n,
-                      int lmax, int layers, double *partial, hipStream_t s);
+                      int lmax, int layers, int chunked, double *partial, hipStream_t s);
 hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, const double *partial,
                           int *tcnt, int *tlist, int *status, hipStream_t s);
 hipError_t launch_collide(int prec, const Lattice &L, const void *A, void *B, const DevParticle *parts,

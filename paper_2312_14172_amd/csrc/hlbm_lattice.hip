@@ -75,16 +75,8 @@ __device__ inline void pull_all(const Lattice &L, const typename ST::S *__restri
 // ---------------------------------------------------------------------------
 // Particle -> fluid coupling evaluated inside the lattice kernels
 // ---------------------------------------------------------------------------
-// Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin.
-// Workgroup b is given tile (b mod 8) * (ntiles / 8) + b / 8, so that each XCD
-// sweeps one contiguous run of tiles in order and the halo rows that
-// neighbouring tiles share are read through the same L2.  The last
-// ntiles mod 8 tiles map to themselves.
-__device__ inline int xcd_tile(int b, int ntiles) {
-  const int per = ntiles >> 3;
-  if (b >= per * 8) return b;
-  return (b & 7) * per + (b >> 3);
-}
+// Tiles are visited in XCD-contiguous runs (xcd_chunk): the halo rows that
+// neighbouring tiles share are read through the same L2.
 
 // A tile's particle, staged in LDS, in the geometry precision G.  Offsets are
 // formed as (cell - floor(X)) + (1/2 - frac(X)) so that FP32 keeps the
@@ -321,7 +313,7 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
   const bool has_af = (L.af[0] != 0.0) || (L.af[1] != 0.0) || (L.af[2] != 0.0);
   const int nx = L.nx, ny = L.ny, nz = L.nz;
 
-  const int tile = xcd_tile(blockIdx.x, L.ntiles);
+  const int tile = xcd_chunk(blockIdx.x, L.ntiles);
   const int tx = tile % L.ntx;
   const int ty = (tile / L.ntx) % L.nty;
   const int tz = tile / (L.ntx * L.nty);
@@ -481,7 +473,7 @@ __global__ __launch_bounds__(256) void k_fields(Lattice L, const typename ST::S 
   using G = typename ST::G;
   __shared__ TileCands<G> tc;
   __shared__ TileFields<G> tf;
-  const int tile = xcd_tile(blockIdx.x, L.ntiles);
+  const int tile = xcd_chunk(blockIdx.x, L.ntiles);
   const int tx = tile % L.ntx;
   const int ty = (tile / L.ntx) % L.nty;
   const int tz = tile / (L.ntx * L.nty);

@@ -285,7 +285,7 @@ __device__ inline int mea_slabs(int lo2, int hi2, int layers) {
   return hi2 < lo2 ? 1 : (hi2 - lo2 + layers) / layers;
 }
 
-// Momentum exchange of one slab: workgroup (order[x], slab) reduces the slab's
+// Momentum exchange of one slab: one workgroup per (particle, slab) reduces the slab's
 // inside cells into one record partial[pid][slab][F, T].  The slab is
 // classified in rounds: each wavefront takes 64 / sx whole x-rows (lane ->
 // (x, row)), the inside cells are compacted into the LDS queue, and full
@@ -293,12 +293,27 @@ __device__ inline int mea_slabs(int lo2, int hi2, int layers) {
 template <class ST, bool O32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST::kind == 2 ? 4 : 3))) void k_mea(Lattice L, const typename ST::S *__restrict__ A,
                                              const DevParticle *__restrict__ parts, const int *__restrict__ order,
-                                             int lmax, int layers, double *__restrict__ partial) {
+                                             int n, int lmax, int layers, int chunked,
+                                             double *__restrict__ partial) {
   __shared__ int queue[512];
   __shared__ int wcnt[4];
   __shared__ double red[4][6];
-  const int pid = order[blockIdx.x];
-  const int slab = blockIdx.y;
+  // work item -> (particle rank in `order`, slab): slab-major (every
+  // particle's first slab, then every second slab, ...), or with `chunked`
+  // the slabs of one particle consecutive and each XCD on a contiguous run of
+  // the order (shared rows read through one L2: pays where the exchange is
+  // bound by HBM traffic, i.e. for many particles)
+  const int nslot = (lmax + layers - 1) / layers;
+  int rank, slab;
+  if (chunked) {
+    const int item = xcd_chunk(blockIdx.x, n * nslot);
+    rank = item / nslot;
+    slab = item - rank * nslot;
+  } else {
+    slab = blockIdx.x / n;
+    rank = blockIdx.x - slab * n;
+  }
+  const int pid = order[rank];
   const DevParticle &sp = parts[pid];
   MeaBox g;
   int hi[3];
@@ -478,14 +493,14 @@ hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int cap
 }
 
 hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevParticle *parts, const int *order, int n,
-                      int lmax, int layers, double *partial, hipStream_t s) {
+                      int lmax, int layers, int chunked, double *partial, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const dim3 grid(n, (lmax + layers - 1) / layers);
+  const dim3 grid(n * ((lmax + layers - 1) / layers));
   HLBM_DISPATCH(prec, {
     if ((unsigned long long)L.N * sizeof(typename ST::S) < (1ull << 32))
-      hipLaunchKernelGGL((k_mea<ST, true>), grid, dim3(256), 0, s, L, (const typename ST::S *)A, parts, order, lmax, layers, partial);
+      hipLaunchKernelGGL((k_mea<ST, true>), grid, dim3(256), 0, s, L, (const typename ST::S *)A, parts, order, n, lmax, layers, chunked, partial);
     else
-      hipLaunchKernelGGL((k_mea<ST, false>), grid, dim3(256), 0, s, L, (const typename ST::S *)A, parts, order, lmax, layers, partial);
+      hipLaunchKernelGGL((k_mea<ST, false>), grid, dim3(256), 0, s, L, (const typename ST::S *)A, parts, order, n, lmax, layers, chunked, partial);
   });
   return hipGetLastError();
 }

@@ -413,13 +413,27 @@ def random_particles_small(n, count, seed, shapes=(SPHERE, ROUNDED_CUBE, SPHEROI
     return np.array(recs)
 
 
+def small_spheres(n=128, count=4200, seed=11, tau=0.6, steps=100, precision="fp32"):
+    """Many small spheres, radius U[1.5, 2.5], RSA (gap >= 1), z walls, tau 0.6,
+    density ratio 2: a parity case with enough particles for the
+    momentum exchange's dispatch for large particle counts."""
+    rng = np.random.default_rng(seed)
+    radii = np.sort(rng.uniform(1.5, 2.5, count))[::-1]
+    pos = rsa_positions(rng, radii, (n, n, n), (0, 0, 1))
+    w = Workload(f"small{count}", (n, n, n), (0, 0, 1), tau, steps, precision, seed=seed,
+                 description=f"{n}^3, z walls, {count} spheres r~U[1.5,2.5], tau={tau}")
+    w.particles = np.array([make_particle(SPHERE, (r,), x, density_ratio=2.0) for r, x in zip(radii, pos)])
+    return w
+
+
 def get(name: str, **kw) -> Workload:
     """Named workloads:
     sphere32   -- 32^3 periodic, one sphere (parity case);
     spheres128 -- 128^3, z walls, 200 spheres r~U[5,7], tau 0.6;
     mixed256   -- 256^3, z walls, 2000 mixed shapes r_eq 6, tau 0.6;
     mixed256_learned -- as mixed256 with the learned indicator for non-spheres;
-    hindered384 -- 384^3, z walls, 11 265 mixed shapes r_eq~U[4,8], tau 0.55.
+    hindered384 -- 384^3, z walls, 11 265 mixed shapes r_eq~U[4,8], tau 0.55;
+    small4200  -- 128^3, z walls, 4200 spheres r~U[1.5,2.5] (parity case).
     """
     if name == "sphere32":
         return single_sphere(**kw)
@@ -431,6 +445,8 @@ def get(name: str, **kw) -> Workload:
         return mixed_shapes(learned=True, **kw)
     if name == "hindered384":
         return hindered_settling(**kw)
+    if name == "small4200":
+        return small_spheres(**kw)
     raise KeyError(name)
 
 

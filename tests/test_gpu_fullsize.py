@@ -1,5 +1,5 @@
-"""Full-size parity: the settling-spheres (128^3, 200 spheres) and mixed-shape
-(256^3, 2000 particles) workloads at their real sizes, in the precisions the
+"""Full-size parity: the settling-spheres (128^3, 200 spheres), mixed-shape
+(256^3, 2000 particles) and many-small-spheres (128^3, 4200) workloads at their real sizes, in the precisions the
 benchmark runs them in and in FP64, against the FP64 CPU oracle over a few
 steps from a non-trivial state (smooth random density and velocity, particles
 moving and spinning).  Every cell's fields and every particle's force, torque
@@ -83,7 +83,10 @@ def _l2rel(a, b, floor=0.0):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), floor * np.sqrt(b.size), 1e-300))
 
 
-CASES = [("spheres128", "fp64"), ("spheres128", "fp32"), ("mixed256", "fp64"), ("mixed256", "fp16s")]
+# small4200: 4200 particles, above the count from which the momentum exchange
+# is dispatched in XCD-contiguous runs of a Morton order
+CASES = [("spheres128", "fp64"), ("spheres128", "fp32"), ("mixed256", "fp64"), ("mixed256", "fp16s"),
+         ("small4200", "fp64"), ("small4200", "fp32")]
 
 
 @pytest.mark.parametrize("name,precision", CASES)
