@@ -150,6 +150,15 @@ int hlbm_set_fields(hlbm_ctx *ctx, const double *rho, const double *u);
  * next hlbm_get_* call. */
 int hlbm_step(hlbm_ctx *ctx, int32_t nsteps);
 
+/* Replace the fluid body acceleration of the configuration (the fluid
+ * outside the solid, as in hlbm_config.fluid_accel) for the steps queued
+ * after this call.  It stands in for a mean pressure gradient: Sec. 5.1
+ * drives a periodic suspension with a pressure gradient, updated as the
+ * settling proceeds, that keeps the net volume flux at zero.  Stream-ordered
+ * (takes effect with the next hlbm_step); non-finite values are rejected
+ * with HLBM_EINVAL and leave the acceleration unchanged. */
+int hlbm_set_fluid_accel(hlbm_ctx *ctx, const double accel[3]);
+
 /* Copy to host the hydrodynamic force F[n][3] and torque T[n][3] on each
  * particle from the last completed step's momentum exchange (zero before the
  * first step), and optionally the current particle records.  Any pointer may

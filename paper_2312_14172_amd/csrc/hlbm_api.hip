@@ -519,6 +519,20 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
   return HLBM_OK;
 }
 
+int hlbm_set_fluid_accel(hlbm_ctx *ctx, const double accel[3]) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  if (!accel) return fail(HLBM_EINVAL, "accel is NULL");
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(accel[k])) return fail(HLBM_EINVAL, "fluid acceleration not finite");
+  // the lattice descriptor is passed by value at each launch, so the new
+  // value applies from the next queued step on
+  for (int k = 0; k < 3; ++k) {
+    ctx->cfg.fluid_accel[k] = accel[k];
+    ctx->L.af[k] = accel[k];
+  }
+  return HLBM_OK;
+}
+
 int hlbm_get_forces(hlbm_ctx *ctx, double *F, double *T, hlbm_particle *state) {
   if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
   int rc = check_status(ctx);

@@ -23,7 +23,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 FIELD_RHO, FIELD_U, FIELD_U_PHYS, FIELD_SOLID = 1, 2, 4, 8
 
 EXPORTED = ["hlbm_workspace_size", "hlbm_init", "hlbm_destroy", "hlbm_set_particles",
-            "hlbm_set_fields", "hlbm_step", "hlbm_get_forces", "hlbm_get_fields",
+            "hlbm_set_fields", "hlbm_step", "hlbm_set_fluid_accel", "hlbm_get_forces", "hlbm_get_fields",
             "hlbm_num_particles", "hlbm_profile_begin", "hlbm_profile_end", "hlbm_mlp_set_params",
             "hlbm_mlp_get_params", "hlbm_mlp_eval", "hlbm_mlp_gradient", "hlbm_train_indicator",
             "hlbm_set_indicator", "hlbm_last_error"]
@@ -89,6 +89,7 @@ def lib():
         L.hlbm_set_particles.argtypes = [vp, i32, vp]
         L.hlbm_set_fields.argtypes = [vp, vp, vp]
         L.hlbm_step.argtypes = [vp, i32]
+        L.hlbm_set_fluid_accel.argtypes = [vp, vp]
         L.hlbm_get_forces.argtypes = [vp, vp, vp, vp]
         L.hlbm_get_fields.argtypes = [vp, ctypes.c_uint32, vp, i32]
         L.hlbm_num_particles.argtypes = [vp, ctypes.POINTER(i32)]
@@ -200,6 +201,11 @@ class Simulation:
         cnt = ctypes.c_int64(0)
         _check(lib().hlbm_profile_end(self._ctx, ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
+
+    def set_fluid_accel(self, accel):
+        """Fluid body acceleration (outside the solid) from the next step on."""
+        a = np.ascontiguousarray(accel, dtype=np.float64).reshape(3)
+        _check(lib().hlbm_set_fluid_accel(self._ctx, a.ctypes.data))
 
     def get_forces(self):
         n = self.num_particles
