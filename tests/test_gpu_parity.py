@@ -209,3 +209,26 @@ def test_set_particles_validation(H):
     with pytest.raises(H.HLBMError):
         sim.set_particles(out)
     sim.close()
+
+
+def test_fluid_accel_changed_between_steps(H):
+    """A body acceleration a on a periodic fluid without particles adds a to
+    the momentum of every cell in each step (the exact-difference source,
+    Sec. 3.2, with B = 0): after n1 steps at a1 and n2 at a2 the bare velocity
+    is n1 a1 + n2 a2 everywhere and the density stays 1.  Non-finite values
+    are rejected and leave the acceleration unchanged."""
+    sim = H.Simulation((20, 12, 9), (0, 0, 0), 0.7, "fp64", max_particles=1, fluid_accel=(1e-5, 0.0, 0.0))
+    sim.set_particles(np.zeros(0, dtype=W.PARTICLE_DTYPE))
+    sim.step(10)
+    sim.set_fluid_accel((0.0, 2e-5, -3e-6))
+    sim.step(5)
+    with pytest.raises(H.HLBMError):
+        sim.set_fluid_accel((float("nan"), 0.0, 0.0))
+    sim.step(1)
+    fl = sim.get_fields(H.FIELD_RHO | H.FIELD_U)
+    sim.close()
+    expect = np.array([10 * 1e-5, 6 * 2e-5, 6 * -3e-6])
+    err_u = float(np.max(np.abs(fl["u"] - expect[:, None])))
+    err_rho = float(np.max(np.abs(fl["rho"] - 1.0)))
+    _log(f"  max|u - n a| {err_u:.2e}  max|rho - 1| {err_rho:.2e}")
+    assert err_u <= 1e-15 and err_rho <= 1e-14
