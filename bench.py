@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f32 (f16 storage)"}
 DEFAULT_PRECISION = {"spheres128": "fp32", "sphere32": "fp64", "mixed256": "fp16s",
-                     "mixed256_learned": "fp16s", "hindered384": "fp32"}
+                     "mixed256_learned": "fp16s", "hindered384": "fp32", "hindered384b": "fp32"}
 # surrogate training settings for the learned-indicator workload
 TRAIN = dict(samples=1_000_000, holdout=100_000, iterations=30000, batch=8192, lr=1e-2, lr_final=1e-5,
              band=0.1, clip=0.25, band_share=0.8, gate_rms=0.05, gate_max=0.5)

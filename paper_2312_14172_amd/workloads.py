@@ -348,7 +348,7 @@ def mixed_shapes(n=256, count=2000, r_eq=6.0, seed=3, tau=0.6, steps=1000, preci
 
 
 def hindered_settling(n=384, count=11265, r_eq_range=(4.0, 8.0), seed=5, tau=0.55, steps=5000,
-                      precision="fp32", density_ratio=2.5, gap=1.0):
+                      precision="fp32", density_ratio=2.5, gap=1.0, name=None):
     """Hindered settling: spheres, rounded cubes and prolate 2:1 spheroids in
     equal thirds with equivalent radius r_eq ~ U[4, 8] (solid fraction ~0.2 at
     11 265 particles in 384^3), uniformly random orientations, voxel-occupancy
@@ -364,7 +364,7 @@ def hindered_settling(n=384, count=11265, r_eq_range=(4.0, 8.0), seed=5, tau=0.5
                               (n, n, n), (0, 0, 1), gap=gap)
     recs = [make_particle(int(shapes[i]), prms[i], pos[k], quat=quats[i], density_ratio=density_ratio)
             for k, i in enumerate(order)]
-    w = Workload(f"hindered{n}", (n, n, n), (0, 0, 1), tau, steps, precision, seed=seed,
+    w = Workload(name or f"hindered{n}", (n, n, n), (0, 0, 1), tau, steps, precision, seed=seed,
                  density_ratio=density_ratio,
                  description=f"{n}^3, z walls, {count} mixed shapes r_eq~U{r_eq_range}, tau={tau}")
     w.particles = np.array(recs)
@@ -433,6 +433,8 @@ def get(name: str, **kw) -> Workload:
     mixed256   -- 256^3, z walls, 2000 mixed shapes r_eq 6, tau 0.6;
     mixed256_learned -- as mixed256 with the learned indicator for non-spheres;
     hindered384 -- 384^3, z walls, 11 265 mixed shapes r_eq~U[4,8], tau 0.55;
+    hindered384b -- as hindered384 with 20 000 particles, r_eq~U[3.30,6.61]
+                  (the same solid fraction 0.2);
     small4200  -- 128^3, z walls, 4200 spheres r~U[1.5,2.5] (parity case).
     """
     if name == "sphere32":
@@ -445,6 +447,8 @@ def get(name: str, **kw) -> Workload:
         return mixed_shapes(learned=True, **kw)
     if name == "hindered384":
         return hindered_settling(**kw)
+    if name == "hindered384b":
+        return hindered_settling(count=20000, r_eq_range=(3.30, 6.61), name="hindered384b", **kw)
     if name == "small4200":
         return small_spheres(**kw)
     raise KeyError(name)

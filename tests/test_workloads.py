@@ -84,3 +84,12 @@ def test_hindered_settling_solid_fraction():
     wl = W.get("hindered384")
     assert len(wl.particles) == 11265
     assert abs(wl.solid_fraction - 0.2) < 2e-3
+
+
+@pytest.mark.slow
+def test_hindered_settling_20000_variant_solid_fraction():
+    """20 000 particles with r_eq ~ U[3.30, 6.61]: the radius range scaled by
+    0.826 so that the stated count and solid fraction 0.2 hold together."""
+    wl = W.get("hindered384b")
+    assert len(wl.particles) == 20000
+    assert abs(wl.solid_fraction - 0.2) < 2e-3
