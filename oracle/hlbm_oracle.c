@@ -71,7 +71,7 @@ typedef struct {
     double af[3];    /* fluid body acceleration (Poiseuille / sphere-array drag) */
 } ocfg;
 
-enum { SH_SPHERE = 0, SH_ROUNDED_CUBE = 1, SH_SPHEROID = 2 };
+enum { SH_SPHERE = 0, SH_ROUNDED_CUBE = 1, SH_SPHEROID = 2, SH_MESH = 3 };
 
 typedef struct {
     double X[3];   /* centre of mass */
@@ -161,21 +161,95 @@ static double sdf_rounded_cube(double h, double rc, const double *p) {
     return outside + inside - rc;
 }
 
+/* Closed triangle mesh (one per run), vertices in the body frame at unit
+ * scale, triangles counter-clockwise seen from outside: g_mesh[t][v][k]. */
+static double *g_mesh = NULL;
+static int g_mesh_nt = 0;
+
+void orc_set_mesh(const double *tri, int nt) {
+    free(g_mesh);
+    g_mesh = (double *)malloc(sizeof(double) * 9 * (size_t)(nt > 0 ? nt : 1));
+    memcpy(g_mesh, tri, sizeof(double) * 9 * (size_t)nt);
+    g_mesh_nt = nt;
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* squared distance from q to the segment [a, b] */
+static double seg_dist2(const double *q, const double *a, const double *b) {
+    double ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, aq[3] = {q[0] - a[0], q[1] - a[1], q[2] - a[2]};
+    double t = dot3(aq, ab) / dot3(ab, ab);
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    double d[3] = {aq[0] - t * ab[0], aq[1] - t * ab[1], aq[2] - t * ab[2]};
+    return dot3(d, d);
+}
+
+/* squared distance from q to the triangle (a, b, c): the foot of the
+ * perpendicular onto the plane if its barycentric coordinates are all
+ * non-negative, else the nearest of the three edges */
+static double tri_dist2(const double *q, const double *a, const double *b, const double *c) {
+    double e0[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e1[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    double n[3] = {e0[1] * e1[2] - e0[2] * e1[1], e0[2] * e1[0] - e0[0] * e1[2], e0[0] * e1[1] - e0[1] * e1[0]};
+    double aq[3] = {q[0] - a[0], q[1] - a[1], q[2] - a[2]};
+    double nn = dot3(n, n);
+    double h = dot3(aq, n) / nn;
+    double f[3] = {aq[0] - h * n[0], aq[1] - h * n[1], aq[2] - h * n[2]}; /* foot - a */
+    /* barycentric coordinates of the foot: f = u e0 + v e1 */
+    double d00 = dot3(e0, e0), d01 = dot3(e0, e1), d11 = dot3(e1, e1);
+    double f0 = dot3(f, e0), f1 = dot3(f, e1);
+    double den = d00 * d11 - d01 * d01;
+    double u = (d11 * f0 - d01 * f1) / den, v = (d00 * f1 - d01 * f0) / den;
+    if (u >= 0.0 && v >= 0.0 && u + v <= 1.0) return h * h * nn;
+    double d = seg_dist2(q, a, b);
+    d = fmin(d, seg_dist2(q, b, c));
+    return fmin(d, seg_dist2(q, c, a));
+}
+
+/* solid angle of the triangle seen from q (Van Oosterom and Strackee 1983) */
+static double tri_solid_angle(const double *q, const double *a, const double *b, const double *c) {
+    double A[3] = {a[0] - q[0], a[1] - q[1], a[2] - q[2]};
+    double B[3] = {b[0] - q[0], b[1] - q[1], b[2] - q[2]};
+    double Cc[3] = {c[0] - q[0], c[1] - q[1], c[2] - q[2]};
+    double la = sqrt(dot3(A, A)), lb = sqrt(dot3(B, B)), lc = sqrt(dot3(Cc, Cc));
+    double bxc[3] = {B[1] * Cc[2] - B[2] * Cc[1], B[2] * Cc[0] - B[0] * Cc[2], B[0] * Cc[1] - B[1] * Cc[0]};
+    double num = dot3(A, bxc);
+    double den = la * lb * lc + dot3(A, B) * lc + dot3(A, Cc) * lb + dot3(B, Cc) * la;
+    return 2.0 * atan2(num, den);
+}
+
+/* Mesh at scale s: unsigned distance = the least distance to a triangle;
+ * inside where the generalised winding number (summed solid angles / 4 pi)
+ * exceeds 1/2. */
+static double sdf_mesh(double s, const double *p) {
+    double q[3] = {p[0] / s, p[1] / s, p[2] / s};
+    double d2 = 1e300, omega = 0.0;
+    for (int t = 0; t < g_mesh_nt; ++t) {
+        const double *a = g_mesh + 9 * t, *b = a + 3, *c = a + 6;
+        d2 = fmin(d2, tri_dist2(q, a, b, c));
+        omega += tri_solid_angle(q, a, b, c);
+    }
+    double d = s * sqrt(d2);
+    return omega > 2.0 * M_PI ? -d : d;
+}
+
 double orc_sdf(int shape, const double *prm, const double *p) {
     switch (shape) {
     case SH_SPHERE: return sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - prm[0];
     case SH_ROUNDED_CUBE: return sdf_rounded_cube(prm[0], prm[1], p);
     case SH_SPHEROID: return sdf_spheroid(prm[0], prm[1], p);
+    case SH_MESH: return sdf_mesh(prm[0], p);
     default: return 1e300;
     }
 }
 
-/* Largest distance of the surface from the centre of mass. */
+/* Largest distance of the surface from the centre of mass (for a mesh the
+ * caller stores it in prm[1]: scale times the largest vertex radius). */
 double orc_circumradius(int shape, const double *prm) {
     switch (shape) {
     case SH_SPHERE: return prm[0];
     case SH_ROUNDED_CUBE: return sqrt(3.0) * (prm[0] - prm[1]) + prm[1];
     case SH_SPHEROID: return fmax(prm[0], prm[1]);
+    case SH_MESH: return prm[1];
     default: return 0.0;
     }
 }

@@ -61,6 +61,7 @@ def lib():
         L.orc_feq.argtypes = [ctypes.c_double, dp, dp]
         L.orc_sdf.argtypes = [ctypes.c_int, dp, dp]
         L.orc_sdf.restype = ctypes.c_double
+        L.orc_set_mesh.argtypes = [dp, ctypes.c_int]
         L.orc_circumradius.argtypes = [ctypes.c_int, dp]
         L.orc_circumradius.restype = ctypes.c_double
         L.orc_indicator.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -166,6 +167,19 @@ class Oracle:
         return out
 
     # ---- particles ------------------------------------------------------
+    # the closed triangle mesh of shape 3 particles (one per process): unit
+    # scale, and its largest vertex radius
+    mesh_rc = 0.0
+
+    @classmethod
+    def set_mesh(cls, vertices, triangles):
+        """vertices [nv, 3] (body frame, unit scale), triangles [nt, 3] vertex
+        indices, counter-clockwise seen from outside."""
+        v = np.asarray(vertices, dtype=np.float64)
+        tri = np.ascontiguousarray(v[np.asarray(triangles)], dtype=np.float64)  # [nt, 3, 3]
+        lib().orc_set_mesh(_dp(tri), len(tri))
+        cls.mesh_rc = float(np.sqrt((tri ** 2).sum(axis=2)).max())
+
     def to_parts(self, particles) -> np.ndarray:
         """Copy a record array with fields pos/quat/vel/omega/mass/volume/
         inertia/param/shape into the oracle's own record layout."""
@@ -180,6 +194,9 @@ class Oracle:
             P["I"] = particles["inertia"]
             P["prm"] = particles["param"]
             P["shape"] = particles["shape"]
+            mesh = P["shape"] == 3
+            if np.any(mesh):  # circumradius of a mesh particle: scale x largest vertex radius
+                P["prm"][mesh, 1] = P["prm"][mesh, 0] * self.mesh_rc
         self._check_parts(P)
         return P
 

@@ -19,8 +19,68 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SPHERE, ROUNDED_CUBE, SPHEROID = 0, 1, 2
-SHAPE_NAMES = {SPHERE: "sphere", ROUNDED_CUBE: "rounded_cube", SPHEROID: "spheroid"}
+SPHERE, ROUNDED_CUBE, SPHEROID, MESH = 0, 1, 2, 3
+SHAPE_NAMES = {SPHERE: "sphere", ROUNDED_CUBE: "rounded_cube", SPHEROID: "spheroid", MESH: "mesh"}
+
+
+# ---------------------------------------------------------------------------
+# Triangle-mesh particles: a closed mesh at unit scale (param[0] = scale)
+# ---------------------------------------------------------------------------
+def icosphere(level: int):
+    """Unit icosphere: the icosahedron with every triangle split into four
+    `level` times, new vertices pushed onto the sphere.  Triangles are
+    counter-clockwise seen from outside."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    v = [np.array(p, dtype=np.float64) / math.sqrt(1 + t * t) for p in v]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+         (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        mid = {}
+
+        def m(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                c = v[a] + v[b]
+                v.append(c / np.linalg.norm(c))
+                mid[key] = len(v) - 1
+            return mid[key]
+
+        f = [t2 for a, b, c in f for t2 in ((a, m(a, b), m(c, a)), (b, m(b, c), m(a, b)), (c, m(c, a), m(b, c)),
+                                            (m(a, b), m(b, c), m(c, a)))]
+    return np.array(v), np.array(f, dtype=np.int32)
+
+
+def bumpy_mesh(level: int = 2, amp: float = 0.5):
+    """A star-shaped closed mesh with cubic symmetry: the icosphere's vertices
+    moved to radius 1 + amp (x^4 + y^4 + z^4 - 3/5) along their direction
+    (bulges along the axes, dents along the diagonals).  Vertices rounded to
+    FP32, the precision the library stores them in."""
+    d, tri = icosphere(level)
+    r = 1.0 + amp * ((d ** 4).sum(axis=1) - 0.6)
+    v = (d * r[:, None]).astype(np.float32).astype(np.float64)
+    return v, tri
+
+
+def mesh_mass_properties(v, tri):
+    """Volume and inertia tensor (unit density) of the solid bounded by a
+    closed, outward-oriented triangle mesh, summed over the tetrahedra
+    (origin, a, b, c): signed volume det[a b c] / 6 and second moments
+    int x x^T = V / 20 (a a^T + b b^T + c c^T + s s^T), s = a + b + c."""
+    a, b, c = v[tri[:, 0]], v[tri[:, 1]], v[tri[:, 2]]
+    vol_t = np.einsum("ij,ij->i", a, np.cross(b, c)) / 6.0
+    ssum = a + b + c
+    second = sum(np.einsum("i,ij,ik->jk", vol_t, x, x) for x in (a, b, c, ssum)) / 20.0
+    vol = float(vol_t.sum())
+    inertia = np.trace(second) * np.eye(3) - second
+    return vol, inertia
+
+
+MESH_UNIT = bumpy_mesh()
+_MESH_VOL, _MESH_INERTIA = mesh_mass_properties(*MESH_UNIT)
+MESH_RC = float(np.sqrt((MESH_UNIT[0] ** 2).sum(axis=1)).max())
 
 PARTICLE_DTYPE = np.dtype([
     ("pos", "<f8", 3), ("quat", "<f8", 4), ("vel", "<f8", 3), ("omega", "<f8", 3),
@@ -70,6 +130,8 @@ def shape_volume(shape: int, prm) -> float:
         return rounded_cube_moments(prm[0], prm[1])[0]
     if shape == SPHEROID:
         return 4.0 / 3.0 * math.pi * prm[0] * prm[1] * prm[1]
+    if shape == MESH:
+        return _MESH_VOL * prm[0] ** 3
     raise ValueError(shape)
 
 
@@ -84,6 +146,8 @@ def shape_inertia(shape: int, prm, mass: float):
     if shape == SPHEROID:  # symmetry axis = body x
         a, b = prm[0], prm[1]
         return (0.4 * mass * b * b, 0.2 * mass * (a * a + b * b), 0.2 * mass * (a * a + b * b))
+    if shape == MESH:  # cubic symmetry: the body axes are principal
+        return tuple(mass / _MESH_VOL * prm[0] ** 2 * np.diag(_MESH_INERTIA))
     raise ValueError(shape)
 
 
@@ -94,6 +158,8 @@ def circumradius(shape: int, prm) -> float:
         return math.sqrt(3.0) * (prm[0] - prm[1]) + prm[1]
     if shape == SPHEROID:
         return float(max(prm[0], prm[1]))
+    if shape == MESH:
+        return MESH_RC * prm[0]
     raise ValueError(shape)
 
 
@@ -110,6 +176,8 @@ def equal_volume_params(shape: int, r_eq: float):
     if shape == SPHEROID:
         b = r_eq / 2 ** (1.0 / 3.0)
         return (2 * b, b, 0.0)
+    if shape == MESH:
+        return ((4.0 / 3.0 * math.pi / _MESH_VOL) ** (1.0 / 3.0) * r_eq, 0.0, 0.0)
     raise ValueError(shape)
 
 
