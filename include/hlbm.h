@@ -73,6 +73,12 @@ extern "C" {
                                (cube of half-extent h - r_c dilated by r_c) */
 #define HLBM_SPHEROID 2     /* param[0] = semi-axis a along body x,
                                param[1] = the two equal semi-axes */
+#define HLBM_MESH 3         /* param[0] = scale of the context's closed triangle
+                               mesh (hlbm_set_mesh; body frame = mesh frame,
+                               whose axes must be principal axes of inertia);
+                               param[1], param[2] are replaced by the library
+                               with scale x (largest vertex radius, least
+                               distance of the surface from the origin) */
 
 /* field selection for hlbm_get_fields */
 #define HLBM_FIELD_RHO 1u    /* rho = sum_i f_i                              (1 plane) */
@@ -96,6 +102,7 @@ typedef struct hlbm_config {
     int32_t learned_samples; /* training + held-out sample capacity (0 = 1.2e6) */
     double learned_max_circumradius; /* largest circumradius of a particle that
                              may use a learned indicator (sizes the tables) */
+    int32_t max_mesh_triangles; /* capacity of the HLBM_MESH shape's mesh, >= 0 */
 } hlbm_config;
 
 typedef struct hlbm_particle {
@@ -107,7 +114,7 @@ typedef struct hlbm_particle {
     double volume;     /* volume used for buoyancy */
     double inertia[3]; /* principal moments of inertia in the body frame, > 0 */
     double param[3];   /* shape parameters, see HLBM_SPHERE etc. */
-    int32_t shape;     /* HLBM_SPHERE | HLBM_ROUNDED_CUBE | HLBM_SPHEROID */
+    int32_t shape;     /* HLBM_SPHERE | HLBM_ROUNDED_CUBE | HLBM_SPHEROID | HLBM_MESH */
     int32_t flags;     /* reserved, must be 0 */
 } hlbm_particle;
 
@@ -150,6 +157,21 @@ int hlbm_set_fields(hlbm_ctx *ctx, const double *rho, const double *u);
  * next hlbm_get_* call. */
 int hlbm_step(hlbm_ctx *ctx, int32_t nsteps);
 
+/* Set the closed triangle mesh of HLBM_MESH particles: vertices[nv][3] in
+ * the body frame at unit scale (FP32), triangles[nt][3] vertex indices,
+ * counter-clockwise seen from outside, enclosing the origin (the centre of
+ * mass).  Copied to the device.  The signed distance of a point is its least
+ * distance to a triangle, negative where the generalised winding number of
+ * the mesh exceeds 1/2; it feeds the indicator (Sec. 3.2 level-set
+ * equation) and the momentum exchange's inside test, like the closed-form
+ * distances of the other shapes.  The paper points to such irregular shapes
+ * (Sec. 5.4) as where the cost of the distance grows; the learned indicator
+ * (hlbm_train_indicator with HLBM_MESH) replaces it there.  Call before
+ * hlbm_set_particles (HLBM_ESTATE if particles are set); HLBM_EUNSUPPORTED
+ * above cfg.max_mesh_triangles; HLBM_EINVAL for bad indices, non-finite
+ * vertices, or a mesh that does not wind once around the origin. */
+int hlbm_set_mesh(hlbm_ctx *ctx, const float *vertices, int32_t nv, const int32_t *triangles, int32_t nt);
+
 /* Replace the fluid body acceleration of the configuration (the fluid
  * outside the solid, as in hlbm_config.fluid_accel) for the steps queued
  * after this call.  It stands in for a mean pressure gradient: Sec. 5.1
@@ -183,7 +205,7 @@ int hlbm_profile_end(hlbm_ctx *ctx, double *collide_ms, int64_t *launches);
 /* ------------------------------------------------------------------------
  * Learned indicator (not part of the paper; its hook is Sec. 5.4: signed
  * distances of non-spherical shapes cost more per lattice node).  For a shape
- * family (HLBM_ROUNDED_CUBE or HLBM_SPHEROID with a fixed aspect) a network
+ * family (HLBM_ROUNDED_CUBE or HLBM_SPHEROID with a fixed aspect, or HLBM_MESH) a network
  * 3 -> 64 -> 64 -> 64 -> 1 with SiLU activations maps a body-frame point
  * divided by the circumradius R_c to d_s / R_c.  BF16 matrix-core products
  * with FP32 accumulation; FP32 master parameters trained with Adam.  When a

@@ -50,7 +50,7 @@ size_t pop_bytes(int precision) { return precision == HLBM_FP64 ? 8 : (precision
 struct Layout {
   size_t fA, fB, parts, order, stage_parts, tcnt[2], tlist[2], partial, status, stage, total;
   // learned indicator (cfg.learned)
-  size_t theta[2], mom1[2], mom2[2], packed[2], gpart, gout, pool, epts, eout, tables;
+  size_t theta[NFAM], mom1[NFAM], mom2[NFAM], packed[NFAM], gpart, gout, pool, epts, eout, tables, mesh;
   long long pool_cap, table_cap;
 };
 
@@ -64,12 +64,14 @@ int validate(const hlbm_config *c) {
       return fail(HLBM_EINVAL, "bc[%d] must be HLBM_BC_PERIODIC or HLBM_BC_WALL", k);
   if (c->precision < HLBM_FP64 || c->precision > HLBM_FP16S) return fail(HLBM_EINVAL, "unknown precision");
   if (c->max_particles < 0) return fail(HLBM_EINVAL, "max_particles < 0");
+  if (c->max_mesh_triangles < 0) return fail(HLBM_EINVAL, "max_mesh_triangles < 0");
   if (!(c->tau > 0.5) || !isfinite(c->tau)) return fail(HLBM_EINVAL, "tau must be > 1/2 (nu > 0)");
   if (!(c->eps > 0.0) || !isfinite(c->eps)) return fail(HLBM_EINVAL, "eps must be > 0");
   if (!isfinite(c->rho_f)) return fail(HLBM_EINVAL, "rho_f not finite");
   if (c->learned != 0 && c->learned != 1) return fail(HLBM_EINVAL, "learned must be 0 or 1");
-  if (c->learned && !(c->learned_max_circumradius > 0 && c->learned_max_circumradius <= 27.0))
-    return fail(HLBM_EINVAL, "learned_max_circumradius must be in (0, 27]");
+  if ((c->learned || c->max_mesh_triangles > 0) &&
+      !(c->learned_max_circumradius > 0 && c->learned_max_circumradius <= 27.0))
+    return fail(HLBM_EINVAL, "learned_max_circumradius must be in (0, 27] (distance tables of learned or mesh shapes)");
   if (c->learned && c->learned_samples < 0) return fail(HLBM_EINVAL, "learned_samples < 0");
   for (int k = 0; k < 3; ++k)
     if (!isfinite(c->gravity[k]) || !isfinite(c->fluid_accel[k]))
@@ -92,6 +94,8 @@ Lattice make_lattice(const hlbm_config *c) {
   L.rho_f = c->rho_f;
   L.tables = nullptr;
   L.table_cap = 0;
+  L.mesh = nullptr;
+  L.mesh_nt = 0;
   return L;
 }
 
@@ -112,10 +116,12 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
   y.partial = off; off += align_up(np * LMAX_CAP * 6 * sizeof(double));
   y.status = off; off += 256;
   y.stage = off; off += align_up((size_t)4 * L.N * sizeof(double));
+  y.mesh = off; off += align_up((size_t)(c->max_mesh_triangles > 0 ? c->max_mesh_triangles : 1) * 3 * sizeof(float4));
   y.pool_cap = 0;
   y.table_cap = 0;
+  const bool tables = c->learned || c->max_mesh_triangles > 0;
   if (c->learned) {
-    for (int f = 0; f < 2; ++f) {
+    for (int f = 0; f < NFAM; ++f) {
       y.theta[f] = off; off += align_up(MLP_PARTIAL * sizeof(float));
       y.mom1[f] = off; off += align_up(MLP_PARTIAL * sizeof(float));
       y.mom2[f] = off; off += align_up(MLP_PARTIAL * sizeof(float));
@@ -127,6 +133,8 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
     y.pool = off; off += align_up((size_t)y.pool_cap * 16);
     y.epts = off; off += align_up((size_t)y.pool_cap * 3 * sizeof(float));
     y.eout = off; off += align_up((size_t)y.pool_cap * sizeof(float));
+  }
+  if (tables) {
     const long long side = (long long)floor(2.0 * (c->learned_max_circumradius + 0.5 * c->eps)) + 2;
     y.table_cap = side * side * side;
     y.tables = off; off += align_up((size_t)np * y.table_cap * sizeof(float));
@@ -159,15 +167,20 @@ struct hlbm_ctx {
   bool profiling;
   std::vector<hipEvent_t> events;  // start/stop pairs around collide launches
   size_t events_used;
-  // learned indicator, index 0: rounded cube, 1: spheroid
-  float *theta[2], *mom1[2], *mom2[2];
-  __bf16 *packed[2];
+  // learned indicator, index 0: rounded cube, 1: spheroid, 2: mesh
+  float *theta[NFAM], *mom1[NFAM], *mom2[NFAM];
+  __bf16 *packed[NFAM];
   float *gpart, *gout, *epts, *eout;
   float4 *pool;
   float *tables;
-  int mode[2];        // HLBM_INDICATOR_EXACT / LEARNED
-  int has_params[2];
-  double aspect[2];   // param[1] / param[0] of the trained shape, 0 = unknown
+  int mode[NFAM];        // HLBM_INDICATOR_EXACT / LEARNED
+  int has_params[NFAM];
+  double aspect[NFAM];   // param[1] / param[0] of the trained shape, 0 = unknown
+  // the mesh of HLBM_MESH particles (unit scale): triangles in the workspace,
+  // largest vertex radius and least distance of the surface from the origin
+  float4 *mesh;
+  double mesh_rc, mesh_rin;
+  bool mesh_particles;  // the current particles include HLBM_MESH ones
 };
 
 namespace {
@@ -188,20 +201,35 @@ int check_status(hlbm_ctx *c) {
 }
 
 bool any_learned(const hlbm_ctx *c) {
-  return c->tables && (c->mode[0] == HLBM_INDICATOR_LEARNED || c->mode[1] == HLBM_INDICATOR_LEARNED);
+  if (!c->tables) return false;
+  for (int f = 0; f < NFAM; ++f)
+    if (c->mode[f] == HLBM_INDICATOR_LEARNED) return true;
+  return false;
 }
 
 int refresh_tables(hlbm_ctx *c) {
-  if (!any_learned(c) || c->n == 0) return HLBM_OK;
-  HIP_TRY(launch_mlp_table(c->L, c->parts, c->n, c->theta[0], c->packed[0], c->theta[1], c->packed[1], c->tables,
-                           c->lay.table_cap, c->stream));
+  if (c->n == 0 || !c->tables) return HLBM_OK;
+  // exact tables of mesh particles without a network
+  if (c->mesh_particles && c->mode[2] != HLBM_INDICATOR_LEARNED)
+    HIP_TRY(launch_mesh_table(c->L, c->parts, c->n, c->tables, c->lay.table_cap, c->stream));
+  if (!any_learned(c)) return HLBM_OK;
+  LearnedNets nets;
+  for (int f = 0; f < NFAM; ++f) {
+    nets.theta[f] = c->theta[f];
+    nets.packed[f] = c->packed[f];
+  }
+  HIP_TRY(launch_mlp_table(c->L, c->parts, c->n, nets, c->tables, c->lay.table_cap, c->stream));
   return HLBM_OK;
 }
 
 int mark_learned(hlbm_ctx *c) {
   if (!c->tables || c->n == 0) return HLBM_OK;
-  HIP_TRY(launch_mark_learned(c->parts, c->n, c->mode[0] == HLBM_INDICATOR_LEARNED, c->aspect[0],
-                              c->mode[1] == HLBM_INDICATOR_LEARNED, c->aspect[1], c->stream));
+  LearnedModes modes;
+  for (int f = 0; f < NFAM; ++f) {
+    modes.on[f] = c->mode[f] == HLBM_INDICATOR_LEARNED;
+    modes.aspect[f] = c->aspect[f];
+  }
+  HIP_TRY(launch_mark_learned(c->parts, c->n, modes, c->stream));
   return refresh_tables(c);
 }
 
@@ -271,7 +299,7 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   c->steps_done = 0;
   c->profiling = false;
   c->events_used = 0;
-  for (int f = 0; f < 2; ++f) {
+  for (int f = 0; f < NFAM; ++f) {
     c->theta[f] = c->mom1[f] = c->mom2[f] = nullptr;
     c->packed[f] = nullptr;
     c->mode[f] = HLBM_INDICATOR_EXACT;
@@ -279,9 +307,12 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
     c->aspect[f] = 0.0;
   }
   c->gpart = c->gout = c->epts = c->eout = c->tables = nullptr;
+  c->mesh = (float4 *)(c->base + lay.mesh);
+  c->mesh_rc = c->mesh_rin = 0.0;
+  c->mesh_particles = false;
   c->pool = nullptr;
   if (cfg->learned) {
-    for (int f = 0; f < 2; ++f) {
+    for (int f = 0; f < NFAM; ++f) {
       c->theta[f] = (float *)(c->base + lay.theta[f]);
       c->mom1[f] = (float *)(c->base + lay.mom1[f]);
       c->mom2[f] = (float *)(c->base + lay.mom2[f]);
@@ -292,6 +323,8 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
     c->pool = (float4 *)(c->base + lay.pool);
     c->epts = (float *)(c->base + lay.epts);
     c->eout = (float *)(c->base + lay.eout);
+  }
+  if (cfg->learned || cfg->max_mesh_triangles > 0) {
     c->tables = (float *)(c->base + lay.tables);
     c->L.tables = c->tables;
     c->L.table_cap = lay.table_cap;
@@ -364,7 +397,9 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
       for (int k = 0; k < lens[a]; ++k)
         if (!isfinite(vals[a][k])) return fail(HLBM_EINVAL, "particle %d: non-finite value", i);
     if (!isfinite(p.mass) || !isfinite(p.volume)) return fail(HLBM_EINVAL, "particle %d: non-finite mass", i);
-    if (p.shape < HLBM_SPHERE || p.shape > HLBM_SPHEROID) return fail(HLBM_EINVAL, "particle %d: bad shape", i);
+    if (p.shape < HLBM_SPHERE || p.shape > HLBM_MESH) return fail(HLBM_EINVAL, "particle %d: bad shape", i);
+    if (p.shape == HLBM_MESH && ctx->L.mesh_nt == 0)
+      return fail(HLBM_ESTATE, "particle %d: HLBM_MESH particle but no mesh (hlbm_set_mesh)", i);
     if (p.flags != 0) return fail(HLBM_EINVAL, "particle %d: flags must be 0", i);
     const double qn = sqrt(p.quat[0] * p.quat[0] + p.quat[1] * p.quat[1] + p.quat[2] * p.quat[2] +
                            p.quat[3] * p.quat[3]);
@@ -379,9 +414,12 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
       if (!(p.param[0] > 0 && p.param[1] >= 0 && p.param[1] <= p.param[0]))
         return fail(HLBM_EINVAL, "particle %d: need h > 0 and 0 <= r_c <= h", i);
       rc = sqrt(3.0) * (p.param[0] - p.param[1]) + p.param[1];
-    } else {
+    } else if (p.shape == HLBM_SPHEROID) {
       if (!(p.param[0] > 0 && p.param[1] > 0)) return fail(HLBM_EINVAL, "particle %d: semi-axes must be > 0", i);
       rc = fmax(p.param[0], p.param[1]);
+    } else {
+      if (!(p.param[0] > 0)) return fail(HLBM_EINVAL, "particle %d: mesh scale must be > 0", i);
+      rc = p.param[0] * ctx->mesh_rc;
     }
     const double reach = rc + fmax(0.5 * ctx->cfg.eps, sqrt(2.0)) + 1.0;
     for (int k = 0; k < 3; ++k) {
@@ -400,8 +438,9 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
     const int tiles_z = std::min(ctx->L.ntz, cells / TZ + 2);
     cap = std::max(cap, tiles_x * tiles_y * tiles_z);
     lmax = std::max(lmax, (int)floor(2.0 * rc) + 2);
-    if (ctx->cfg.learned && p.shape != HLBM_SPHERE && rc > ctx->cfg.learned_max_circumradius)
-      return fail(HLBM_EINVAL, "particle %d: circumradius %.3f above learned_max_circumradius", i, rc);
+    if ((ctx->cfg.learned || p.shape == HLBM_MESH) && p.shape != HLBM_SPHERE &&
+        rc > ctx->cfg.learned_max_circumradius)
+      return fail(HLBM_EINVAL, "particle %d: circumradius %.3f above learned_max_circumradius (table size)", i, rc);
   }
   if (lmax > LMAX_CAP) return fail(HLBM_EUNSUPPORTED, "circumradius too large");
   HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -438,12 +477,24 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
     if (pa[0] != pb[0]) return pa[0] < pb[0];
     return a < b;
   });
+  // mesh particles carry scale x (largest vertex radius, least surface
+  // distance from the centre) in param[1], param[2]
+  std::vector<hlbm_particle> staged(host, host + n);
+  for (auto &p : staged)
+    if (p.shape == HLBM_MESH) {
+      p.param[1] = p.param[0] * ctx->mesh_rc;
+      p.param[2] = p.param[0] * ctx->mesh_rin;
+    }
   if (n > 0) {
-    HIP_TRY(hipMemcpyAsync(ctx->stage_parts, host, sizeof(hlbm_particle) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->stage_parts, staged.data(), sizeof(hlbm_particle) * n, hipMemcpyHostToDevice,
+                           ctx->stream));
     HIP_TRY(hipMemcpyAsync(ctx->order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(launch_prepare(ctx->L, ctx->stage_parts, ctx->parts, n, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));  // the host copies above are released on return
   }
   ctx->n = n;
+  ctx->mesh_particles = false;
+  for (int i = 0; i < n; ++i) ctx->mesh_particles |= host[i].shape == HLBM_MESH;
   ctx->mea_chunked = chunked ? 1 : 0;
   ctx->bin_cap = cap;
   ctx->lmax = lmax;
@@ -516,6 +567,78 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
     ctx->fB = t;
     ctx->steps_done++;
   }
+  return HLBM_OK;
+}
+
+namespace {
+// host geometry of the mesh: least distance of a triangle from the origin and
+// the triangle's solid angle seen from the origin
+double h_dot(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+void h_cross(const double *a, const double *b, double *o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+double h_seg_dist2(const double *a, const double *b) {  // from the origin
+  const double ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  double t = -h_dot(a, ab) / h_dot(ab, ab);
+  t = t < 0 ? 0 : (t > 1 ? 1 : t);
+  const double d[3] = {a[0] + t * ab[0], a[1] + t * ab[1], a[2] + t * ab[2]};
+  return h_dot(d, d);
+}
+double h_tri_dist2(const double *a, const double *b, const double *c) {
+  const double e0[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e1[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+  double n[3];
+  h_cross(e0, e1, n);
+  const double nn = h_dot(n, n), h = -h_dot(a, n) / nn;
+  const double f[3] = {-a[0] - h * n[0], -a[1] - h * n[1], -a[2] - h * n[2]};
+  const double d00 = h_dot(e0, e0), d01 = h_dot(e0, e1), d11 = h_dot(e1, e1);
+  const double f0 = h_dot(f, e0), f1 = h_dot(f, e1), den = d00 * d11 - d01 * d01;
+  const double u = (d11 * f0 - d01 * f1) / den, v = (d00 * f1 - d01 * f0) / den;
+  if (u >= 0 && v >= 0 && u + v <= 1) return h * h * nn;
+  return std::min(h_seg_dist2(a, b), std::min(h_seg_dist2(b, c), h_seg_dist2(c, a)));
+}
+double h_solid_angle(const double *a, const double *b, const double *c) {
+  double bxc[3];
+  h_cross(b, c, bxc);
+  const double la = sqrt(h_dot(a, a)), lb = sqrt(h_dot(b, b)), lc = sqrt(h_dot(c, c));
+  return 2.0 * atan2(h_dot(a, bxc), la * lb * lc + h_dot(a, b) * lc + h_dot(a, c) * lb + h_dot(b, c) * la);
+}
+}  // namespace
+
+int hlbm_set_mesh(hlbm_ctx *ctx, const float *vertices, int32_t nv, const int32_t *triangles, int32_t nt) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  if (!vertices || !triangles) return fail(HLBM_EINVAL, "NULL argument");
+  if (ctx->n > 0) return fail(HLBM_ESTATE, "set the mesh before the particles");
+  if (nv < 4 || nt < 4) return fail(HLBM_EINVAL, "a closed mesh needs >= 4 vertices and triangles");
+  if (nt > ctx->cfg.max_mesh_triangles)
+    return fail(HLBM_EUNSUPPORTED, "%d triangles above max_mesh_triangles = %d", nt, ctx->cfg.max_mesh_triangles);
+  for (int k = 0; k < 3 * nv; ++k)
+    if (!isfinite(vertices[k])) return fail(HLBM_EINVAL, "vertex coordinate %d not finite", k);
+  std::vector<float4> tri((size_t)3 * nt);
+  double rc = 0.0, rin2 = 1e300, omega = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    double v[3][3];
+    for (int j = 0; j < 3; ++j) {
+      const int id = triangles[3 * t + j];
+      if (id < 0 || id >= nv) return fail(HLBM_EINVAL, "triangle %d: vertex index %d out of range", t, id);
+      for (int k = 0; k < 3; ++k) v[j][k] = (double)vertices[3 * id + k];
+      tri[3 * t + j] = make_float4(vertices[3 * id], vertices[3 * id + 1], vertices[3 * id + 2], 0.f);
+      rc = std::max(rc, sqrt(h_dot(v[j], v[j])));
+    }
+    rin2 = std::min(rin2, h_tri_dist2(v[0], v[1], v[2]));
+    omega += h_solid_angle(v[0], v[1], v[2]);
+  }
+  // winding number of the origin: 1 for a closed, outward-oriented mesh around it
+  if (!(fabs(omega / (4.0 * M_PI) - 1.0) < 1e-3))
+    return fail(HLBM_EINVAL, "the mesh must be closed, enclose the origin and be counter-clockwise seen from outside "
+                             "(winding number of the origin %.4f)", omega / (4.0 * M_PI));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(hipMemcpy(ctx->mesh, tri.data(), sizeof(float4) * tri.size(), hipMemcpyHostToDevice));
+  ctx->L.mesh = ctx->mesh;
+  ctx->L.mesh_nt = nt;
+  ctx->mesh_rc = rc;
+  ctx->mesh_rin = sqrt(rin2);
   return HLBM_OK;
 }
 
@@ -603,15 +726,16 @@ int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_de
 static int family(hlbm_ctx *ctx, int32_t shape, int *f) {
   if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
   if (!ctx->cfg.learned) return fail(HLBM_ESTATE, "the context was created without cfg.learned");
-  if (shape != HLBM_ROUNDED_CUBE && shape != HLBM_SPHEROID)
-    return fail(HLBM_EINVAL, "learned indicators exist for HLBM_ROUNDED_CUBE and HLBM_SPHEROID");
-  *f = shape == HLBM_ROUNDED_CUBE ? 0 : 1;
+  if (shape != HLBM_ROUNDED_CUBE && shape != HLBM_SPHEROID && shape != HLBM_MESH)
+    return fail(HLBM_EINVAL, "learned indicators exist for HLBM_ROUNDED_CUBE, HLBM_SPHEROID and HLBM_MESH");
+  *f = shape - 1;
   return HLBM_OK;
 }
 
-static double circumradius_host(int shape, const double *prm) {
+static double circumradius_host(const hlbm_ctx *ctx, int shape, const double *prm) {
   if (shape == HLBM_ROUNDED_CUBE) return sqrt(3.0) * (prm[0] - prm[1]) + prm[1];
   if (shape == HLBM_SPHEROID) return fmax(prm[0], prm[1]);
+  if (shape == HLBM_MESH) return prm[0] * ctx->mesh_rc;
   return prm[0];
 }
 
@@ -688,8 +812,12 @@ int hlbm_train_indicator(hlbm_ctx *ctx, int32_t shape, const double *param, cons
   if (rc) return rc;
   if (!param || !o) return fail(HLBM_EINVAL, "NULL argument");
   if (!ctx->has_params[f]) return fail(HLBM_ESTATE, "set initial parameters first (hlbm_mlp_set_params)");
-  if (!(param[0] > 0 && param[1] > 0) || (shape == HLBM_ROUNDED_CUBE && param[1] > param[0]))
+  if (shape == HLBM_MESH) {
+    if (ctx->L.mesh_nt == 0) return fail(HLBM_ESTATE, "no mesh (hlbm_set_mesh)");
+    if (!(param[0] > 0)) return fail(HLBM_EINVAL, "bad shape parameters");
+  } else if (!(param[0] > 0 && param[1] > 0) || (shape == HLBM_ROUNDED_CUBE && param[1] > param[0])) {
     return fail(HLBM_EINVAL, "bad shape parameters");
+  }
   if (o->samples < 64 || o->holdout < 1 || (long long)o->samples + o->holdout > ctx->lay.pool_cap)
     return fail(HLBM_EINVAL, "samples + holdout must fit the sample capacity %lld", ctx->lay.pool_cap);
   if (o->batch < 32 || o->batch > o->samples || o->iterations < 1)
@@ -698,13 +826,14 @@ int hlbm_train_indicator(hlbm_ctx *ctx, int32_t shape, const double *param, cons
         o->band_share >= 0 && o->band_share <= 1))
     return fail(HLBM_EINVAL, "bad learning rate / box / band / clip");
   const auto t0 = std::chrono::steady_clock::now();
-  const double Rc = circumradius_host(shape, param);
+  const double Rc = circumradius_host(ctx, shape, param);
   const double p0 = param[0] / Rc, p1 = param[1] / Rc;
   hipStream_t s = ctx->stream;
   HIP_TRY(hipStreamSynchronize(s));
-  HIP_TRY(mlp_samples(shape, p0, p1, o->seed, o->samples, o->box, o->band, o->clip, o->band_share, ctx->pool, s));
-  HIP_TRY(mlp_samples(shape, p0, p1, o->seed ^ 0x5bd1e995ull, o->holdout, o->box, o->band, o->clip, 1.0,
-                      ctx->pool + o->samples, s));
+  HIP_TRY(mlp_samples(shape, p0, p1, ctx->L.mesh, ctx->L.mesh_nt, o->seed, o->samples, o->box, o->band, o->clip,
+                      o->band_share, ctx->pool, s));
+  HIP_TRY(mlp_samples(shape, p0, p1, ctx->L.mesh, ctx->L.mesh_nt, o->seed ^ 0x5bd1e995ull, o->holdout, o->box,
+                      o->band, o->clip, 1.0, ctx->pool + o->samples, s));
   HIP_TRY(launch_fill_int((int *)ctx->mom1[f], 0, MLP_PARTIAL, s));
   HIP_TRY(launch_fill_int((int *)ctx->mom2[f], 0, MLP_PARTIAL, s));
   const int nbatches = o->samples / o->batch;
@@ -757,7 +886,8 @@ int hlbm_train_indicator(hlbm_ctx *ctx, int32_t shape, const double *param, cons
     rep->iterations = o->iterations;
     rep->accepted = ok ? 1 : 0;
   }
-  ctx->aspect[f] = param[1] / param[0];
+  // the mesh family's particles all have param[1] / param[0] = largest vertex radius
+  ctx->aspect[f] = shape == HLBM_MESH ? ctx->mesh_rc : param[1] / param[0];
   ctx->mode[f] = ok ? HLBM_INDICATOR_LEARNED : HLBM_INDICATOR_EXACT;
   return mark_learned(ctx);
 }

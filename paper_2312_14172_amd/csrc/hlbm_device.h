@@ -72,6 +72,8 @@ struct Lattice {
   double g[3];
   const float *tables;  // per-particle learned distance tables (NULL: none)
   long long table_cap;  // floats per particle table
+  const float4 *mesh;   // triangles of the mesh shape: 3 vertices each (unit scale)
+  int mesh_nt;          // number of triangles (0: no mesh)
 };
 
 // Particle record on the device (FP64).  The first block mirrors the public
@@ -85,7 +87,7 @@ struct DevParticle {
   double Th[3];    // hydrodynamic torque of the last momentum exchange
   int shape, flags;
   int lo[3], hi[3];  // cells that can have B > 0 (centre within rc + eps/2), unwrapped
-  int learned;       // 1: d_s comes from the particle's learned distance table
+  int learned;       // distance table: 0 none, 1 learned (network), 2 exact (mesh)
 };
 
 // Tiles touched by a cell range along one axis (wrapped on periodic axes),
@@ -250,6 +252,82 @@ __device__ inline G sdf_for_indicator(int shape, G p0, G p1, G ia2, G ib2, G b0,
     if (dabs(s - G(1)) * dmin(p0, p1) >= half_eps) return k <= G(1) ? G(-1e30) : G(1e30);
   }
   return sdf_body<G>(shape, p0, p1, b0, b1, b2);
+}
+
+// ---------------------------------------------------------------------------
+// Triangle-mesh particles (shape 3): a closed mesh at unit scale, triangles
+// counter-clockwise seen from outside, scaled by param[0].  The unsigned
+// distance is the least distance to a triangle (the foot of the perpendicular
+// on the triangle's plane when it falls inside the triangle, else the nearest
+// edge); the sign comes from the generalised winding number, the summed solid
+// angles of the triangles over 4 pi (Van Oosterom and Strackee's formula for
+// the solid angle of a triangle), which is 1 inside and 0 outside.
+// ---------------------------------------------------------------------------
+__device__ inline double datan2(double y, double x) { return atan2(y, x); }
+__device__ inline float datan2(float y, float x) { return atan2f(y, x); }
+
+template <typename G>
+struct V3 {
+  G x, y, z;
+};
+template <typename G>
+__device__ inline V3<G> v3sub(V3<G> a, V3<G> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename G>
+__device__ inline G v3dot(V3<G> a, V3<G> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename G>
+__device__ inline V3<G> v3cross(V3<G> a, V3<G> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename G>
+__device__ inline V3<G> v3load(const float4 &v) { return {(G)v.x, (G)v.y, (G)v.z}; }
+
+// squared distance from q to the segment [a, b]
+template <typename G>
+__device__ inline G seg_dist2(V3<G> q, V3<G> a, V3<G> b) {
+  const V3<G> ab = v3sub(b, a), aq = v3sub(q, a);
+  G t = v3dot(aq, ab) / v3dot(ab, ab);
+  t = dmin(dmax(t, G(0)), G(1));
+  const V3<G> d = {aq.x - t * ab.x, aq.y - t * ab.y, aq.z - t * ab.z};
+  return v3dot(d, d);
+}
+
+template <typename G>
+__device__ inline G tri_dist2(V3<G> q, V3<G> a, V3<G> b, V3<G> c) {
+  const V3<G> e0 = v3sub(b, a), e1 = v3sub(c, a), aq = v3sub(q, a);
+  const V3<G> n = v3cross(e0, e1);
+  const G nn = v3dot(n, n);
+  const G h = v3dot(aq, n) / nn;
+  const V3<G> f = {aq.x - h * n.x, aq.y - h * n.y, aq.z - h * n.z};
+  const G d00 = v3dot(e0, e0), d01 = v3dot(e0, e1), d11 = v3dot(e1, e1);
+  const G f0 = v3dot(f, e0), f1 = v3dot(f, e1);
+  const G den = d00 * d11 - d01 * d01;
+  const G u = (d11 * f0 - d01 * f1) / den, v = (d00 * f1 - d01 * f0) / den;
+  if (u >= G(0) && v >= G(0) && u + v <= G(1)) return h * h * nn;
+  return dmin(seg_dist2(q, a, b), dmin(seg_dist2(q, b, c), seg_dist2(q, c, a)));
+}
+
+template <typename G>
+__device__ inline G tri_solid_angle(V3<G> q, V3<G> a, V3<G> b, V3<G> c) {
+  const V3<G> A = v3sub(a, q), B = v3sub(b, q), C = v3sub(c, q);
+  const G la = dsqrt(v3dot(A, A)), lb = dsqrt(v3dot(B, B)), lc = dsqrt(v3dot(C, C));
+  const G num = v3dot(A, v3cross(B, C));
+  const G den = la * lb * lc + v3dot(A, B) * lc + v3dot(A, C) * lb + v3dot(B, C) * la;
+  return G(2) * datan2(num, den);
+}
+
+// Signed distance of the body-frame point (x, y, z) to the mesh at `scale`.
+template <typename G>
+__device__ inline G mesh_sdf(const float4 *tri, int nt, G scale, G x, G y, G z) {
+  const G is = G(1) / scale;
+  const V3<G> q = {x * is, y * is, z * is};
+  G d2 = G(1e30), omega = G(0);
+  for (int t = 0; t < nt; ++t) {
+    const V3<G> a = v3load<G>(tri[3 * t]), b = v3load<G>(tri[3 * t + 1]), c = v3load<G>(tri[3 * t + 2]);
+    d2 = dmin(d2, tri_dist2(q, a, b, c));
+    omega += tri_solid_angle(q, a, b, c);
+  }
+  const G d = scale * dsqrt(d2);
+  return omega > G(6.283185307179586) ? -d : d;
 }
 
 // Inside test d_s <= 0 from the shape's implicit form (FP64).

@@ -10,11 +10,21 @@ namespace hlbm {
 
 hipError_t launch_prepare(const Lattice &L, const hlbm_particle *in, DevParticle *out, int n, hipStream_t s);
 hipError_t launch_fill_int(int *p, int v, int n, hipStream_t s);
-hipError_t launch_mark_learned(DevParticle *parts, int n, int mode_cube, double aspect_cube, int mode_sph,
-                               double aspect_sph, hipStream_t s);
-hipError_t launch_mlp_table(const Lattice &L, const DevParticle *parts, int n, const float *theta_cube,
-                            const __bf16 *packed_cube, const float *theta_sph, const __bf16 *packed_sph,
+// learned-indicator families: 0 rounded cube, 1 spheroid, 2 mesh (shape - 1)
+constexpr int NFAM = 3;
+struct LearnedModes {
+  int on[NFAM];          // family uses its learned indicator
+  double aspect[NFAM];   // param[1] / param[0] of the trained shape
+};
+struct LearnedNets {
+  const float *theta[NFAM];
+  const __bf16 *packed[NFAM];
+};
+hipError_t launch_mark_learned(DevParticle *parts, int n, const LearnedModes &modes, hipStream_t s);
+hipError_t launch_mlp_table(const Lattice &L, const DevParticle *parts, int n, const LearnedNets &nets,
                             float *tables, long long cap, hipStream_t s);
+hipError_t launch_mesh_table(const Lattice &L, const DevParticle *parts, int n, float *tables, long long cap,
+                             hipStream_t s);
 hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int cap, int *tcnt, int *tlist,
                       int *status, hipStream_t s);
 hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevParticle *parts, const int *order, int n,

@@ -134,8 +134,9 @@ __device__ inline void load_candidates(const Lattice &L, const DevParticle *part
     c.p1 = (G)p.prm[1];
     const double ro = p.rc + 0.5 * L.eps;
     c.reach2 = (G)(ro * ro);
-    // inscribed radius: sphere r, rounded cube h, spheroid min(a, b)
-    const double rin = p.shape == 2 ? fmin(p.prm[0], p.prm[1]) : p.prm[0];
+    // inscribed radius: sphere r, rounded cube h, spheroid min(a, b), mesh
+    // (stored by the host) scale x the least distance of its surface from the centre
+    const double rin = p.shape == 2 ? fmin(p.prm[0], p.prm[1]) : (p.shape == 3 ? p.prm[2] : p.prm[0]);
     const double ri = rin - 0.5 * L.eps;
     c.inner2 = ri > 0.0 ? (G)(ri * ri) : G(-1);
     c.ia2 = (G)(1.0 / (p.prm[0] * p.prm[0]));

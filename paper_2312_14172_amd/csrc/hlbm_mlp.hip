@@ -13,6 +13,7 @@
 // between layers.  Weight-gradient products (contraction over samples) go
 // through LDS to transpose activations and errors.
 #include "hlbm_device.h"
+#include "hlbm_internal.h"
 #include "hlbm_mlp.h"
 
 namespace hlbm {
@@ -359,8 +360,8 @@ __device__ inline double uniform01(uint64_t seed, uint64_t idx, int k) {
   return (double)(splitmix64(seed ^ splitmix64(idx * 64 + (uint64_t)k)) >> 11) * (1.0 / 9007199254740992.0);
 }
 
-__global__ void k_sdf_samples(int shape, double p0, double p1, uint64_t seed, int n, double box, double band,
-                              double clip, double band_share, float4 *__restrict__ out) {
+__global__ void k_sdf_samples(int shape, double p0, double p1, const float4 *mesh, int mesh_nt, uint64_t seed, int n,
+                              double box, double band, double clip, double band_share, float4 *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const bool want_band = uniform01(seed, i, 1000) < band_share;
@@ -369,7 +370,7 @@ __global__ void k_sdf_samples(int shape, double p0, double p1, uint64_t seed, in
     x = (2.0 * uniform01(seed, i, 3 * k) - 1.0) * box;
     y = (2.0 * uniform01(seed, i, 3 * k + 1) - 1.0) * box;
     z = (2.0 * uniform01(seed, i, 3 * k + 2) - 1.0) * box;
-    d = sdf_body<double>(shape, p0, p1, x, y, z);
+    d = shape == 3 ? mesh_sdf<double>(mesh, mesh_nt, p0, x, y, z) : sdf_body<double>(shape, p0, p1, x, y, z);
     if (!want_band || fabs(d) <= band) break;
   }
   const double t = fmax(-clip, fmin(clip, d));
@@ -389,21 +390,21 @@ __global__ void k_sdf_samples(int shape, double p0, double p1, uint64_t seed, in
 constexpr int TAB_CHUNK = 128;
 
 __global__ __launch_bounds__(64) void k_mlp_table(Lattice L, const DevParticle *__restrict__ parts,
-                                                  const float *th_cube, const __bf16 *pk_cube, const float *th_sph,
-                                                  const __bf16 *pk_sph, float *__restrict__ tables, long long cap) {
+                                                  LearnedNets nets, float *__restrict__ tables, long long cap) {
   __shared__ int qidx[TAB_CHUNK];
   __shared__ float qx[3][TAB_CHUNK];
   const int pid = blockIdx.y;
   const DevParticle &p = parts[pid];
-  if (!p.learned) return;
+  if (p.learned != 1) return;
   const int sx = p.hi[0] - p.lo[0] + 1, sy = p.hi[1] - p.lo[1] + 1, sz = p.hi[2] - p.lo[2] + 1;
   const int total = sx * sy * sz;
   const int base = blockIdx.x * TAB_CHUNK;
   if (base >= total) return;
-  const MlpArgs A = mlp_args(p.shape == 1 ? th_cube : th_sph, p.shape == 1 ? pk_cube : pk_sph);
+  const int fam = min(max(p.shape - 1, 0), NFAM - 1);  // learned particles are shapes 1..3
+  const MlpArgs A = mlp_args(nets.theta[fam], nets.packed[fam]);
   const int l = threadIdx.x, g = l >> 4, li = l & 15;
   const double rc = p.rc, inv = 1.0 / rc;
-  const double rin = p.shape == 2 ? fmin(p.prm[0], p.prm[1]) : p.prm[0];
+  const double rin = p.shape == 2 ? fmin(p.prm[0], p.prm[1]) : (p.shape == 3 ? p.prm[2] : p.prm[0]);
   const double lo2 = rin - 0.5 * L.eps, hi2 = rc + 0.5 * L.eps;
   float *tab = tables + (size_t)pid * cap;
   // classify; compact the shell cells (in cell order)
@@ -458,16 +459,52 @@ __global__ __launch_bounds__(64) void k_mlp_table(Lattice L, const DevParticle *
   }
 }
 
+// Exact distance table of the mesh particles without a network (learned ==
+// 2): same layout, shell and early-outs as k_mlp_table, with the mesh's signed
+// distance (FP64, stored in FP32) on the shell.  One thread per coupling-box
+// cell; grid = (ceil(cap / 256), n).
+__global__ __launch_bounds__(256) void k_mesh_table(Lattice L, const DevParticle *__restrict__ parts,
+                                                   float *__restrict__ tables, long long cap) {
+  const int pid = blockIdx.y;
+  const DevParticle &p = parts[pid];
+  if (p.learned != 2) return;
+  const int sx = p.hi[0] - p.lo[0] + 1, sy = p.hi[1] - p.lo[1] + 1, sz = p.hi[2] - p.lo[2] + 1;
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= sx * sy * sz) return;
+  const double d0 = (p.lo[0] + idx % sx + 0.5) - p.X[0];
+  const double d1 = (p.lo[1] + (idx / sx) % sy + 0.5) - p.X[1];
+  const double d2 = (p.lo[2] + idx / (sx * sy) + 0.5) - p.X[2];
+  const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+  const double lo2 = p.prm[2] - 0.5 * L.eps, hi2 = p.rc + 0.5 * L.eps;
+  float *tab = tables + (size_t)pid * cap;
+  if (r2 > hi2 * hi2) {
+    tab[idx] = 1e30f;
+  } else if (lo2 > 0.0 && r2 < lo2 * lo2) {
+    tab[idx] = -1e30f;
+  } else {
+    const double *R = p.R;
+    const double b0 = R[0] * d0 + R[3] * d1 + R[6] * d2;
+    const double b1 = R[1] * d0 + R[4] * d1 + R[7] * d2;
+    const double b2 = R[2] * d0 + R[5] * d1 + R[8] * d2;
+    tab[idx] = (float)mesh_sdf<double>(L.mesh, L.mesh_nt, p.prm[0], b0, b1, b2);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_mlp_table(const Lattice &L, const DevParticle *parts, int n, const float *theta_cube,
-                            const __bf16 *packed_cube, const float *theta_sph, const __bf16 *packed_sph,
+hipError_t launch_mesh_table(const Lattice &L, const DevParticle *parts, int n, float *tables, long long cap,
+                             hipStream_t s) {
+  if (n <= 0 || !tables || L.mesh_nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mesh_table, dim3((unsigned)((cap + 255) / 256), n), dim3(256), 0, s, L, parts, tables, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_table(const Lattice &L, const DevParticle *parts, int n, const LearnedNets &nets,
                             float *tables, long long cap, hipStream_t s) {
   if (n <= 0 || !tables) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_table, dim3((unsigned)((cap + TAB_CHUNK - 1) / TAB_CHUNK), n), dim3(64), 0, s, L, parts,
-                     theta_cube,
-                     packed_cube, theta_sph, packed_sph, tables, cap);
+                     nets, tables, cap);
   return hipGetLastError();
 }
 
@@ -505,11 +542,11 @@ hipError_t mlp_reduce_adam(float *theta, float *m, float *v, const float *partia
   return hipGetLastError();
 }
 
-hipError_t mlp_samples(int shape, double p0, double p1, uint64_t seed, int n, double box, double band, double clip,
-                       double band_share, float4 *out, hipStream_t s) {
+hipError_t mlp_samples(int shape, double p0, double p1, const float4 *mesh, int mesh_nt, uint64_t seed, int n,
+                       double box, double band, double clip, double band_share, float4 *out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sdf_samples, dim3((n + 255) / 256), dim3(256), 0, s, shape, p0, p1, seed, n, box, band,
-                     clip, band_share, out);
+  hipLaunchKernelGGL(k_sdf_samples, dim3((n + 255) / 256), dim3(256), 0, s, shape, p0, p1, mesh, mesh_nt, seed, n,
+                     box, band, clip, band_share, out);
   return hipGetLastError();
 }
 

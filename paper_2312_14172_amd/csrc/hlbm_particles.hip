@@ -31,6 +31,7 @@ __device__ inline void quat_rot(const double *q, double *R) {
 __device__ inline double circumradius(int shape, double p0, double p1) {
   if (shape == 0) return p0;
   if (shape == 1) return 1.7320508075688772 * (p0 - p1) + p1;
+  if (shape == 3) return p1;  // mesh: scale x largest vertex radius, stored by the host
   return fmax(p0, p1);
 }
 
@@ -85,16 +86,16 @@ __global__ void k_prepare(Lattice L, const hlbm_particle *in, DevParticle *out, 
 
 // Mark the particles whose shape family uses its learned indicator (and whose
 // aspect matches the trained one).
-__global__ void k_mark_learned(DevParticle *parts, int n, int mode_cube, double aspect_cube, int mode_sph,
-                               double aspect_sph) {
+__global__ void k_mark_learned(DevParticle *parts, int n, LearnedModes modes) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   DevParticle &p = parts[i];
   const double asp = p.prm[1] / p.prm[0];
   int on = 0;
-  if (p.shape == 1 && mode_cube) on = fabs(asp - aspect_cube) <= 1e-6 * aspect_cube;
-  if (p.shape == 2 && mode_sph) on = fabs(asp - aspect_sph) <= 1e-6 * aspect_sph;
-  p.learned = on;
+  const int f = p.shape - 1;  // family: rounded cube, spheroid, mesh
+  if (f >= 0 && f < 3 && modes.on[f]) on = fabs(asp - modes.aspect[f]) <= 1e-6 * modes.aspect[f];
+  // mesh particles always read a distance table: the network's, or the exact one
+  p.learned = on ? 1 : (p.shape == 3 ? 2 : 0);
 }
 
 __global__ void k_fill_int(int *p, int v, int n) {
@@ -471,11 +472,9 @@ hipError_t launch_prepare(const Lattice &L, const hlbm_particle *in, DevParticle
   return hipGetLastError();
 }
 
-hipError_t launch_mark_learned(DevParticle *parts, int n, int mode_cube, double aspect_cube, int mode_sph,
-                               double aspect_sph, hipStream_t s) {
+hipError_t launch_mark_learned(DevParticle *parts, int n, const LearnedModes &modes, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mark_learned, dim3(blocks_for(n, 128)), dim3(128), 0, s, parts, n, mode_cube, aspect_cube,
-                     mode_sph, aspect_sph);
+  hipLaunchKernelGGL(k_mark_learned, dim3(blocks_for(n, 128)), dim3(128), 0, s, parts, n, modes);
   return hipGetLastError();
 }
 

@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 FIELD_RHO, FIELD_U, FIELD_U_PHYS, FIELD_SOLID = 1, 2, 4, 8
 
 EXPORTED = ["hlbm_workspace_size", "hlbm_init", "hlbm_destroy", "hlbm_set_particles",
-            "hlbm_set_fields", "hlbm_step", "hlbm_set_fluid_accel", "hlbm_get_forces", "hlbm_get_fields",
+            "hlbm_set_fields", "hlbm_step", "hlbm_set_fluid_accel", "hlbm_set_mesh", "hlbm_get_forces",
+            "hlbm_get_fields",
             "hlbm_num_particles", "hlbm_profile_begin", "hlbm_profile_end", "hlbm_mlp_set_params",
             "hlbm_mlp_get_params", "hlbm_mlp_eval", "hlbm_mlp_gradient", "hlbm_train_indicator",
             "hlbm_set_indicator", "hlbm_last_error"]
@@ -38,7 +39,8 @@ class hlbm_config(ctypes.Structure):
                 ("eps", ctypes.c_double), ("rho_f", ctypes.c_double),
                 ("gravity", ctypes.c_double * 3), ("fluid_accel", ctypes.c_double * 3),
                 ("stream", ctypes.c_void_p), ("learned", ctypes.c_int32),
-                ("learned_samples", ctypes.c_int32), ("learned_max_circumradius", ctypes.c_double)]
+                ("learned_samples", ctypes.c_int32), ("learned_max_circumradius", ctypes.c_double),
+                ("max_mesh_triangles", ctypes.c_int32)]
 
 
 class hlbm_train_opts(ctypes.Structure):
@@ -90,6 +92,7 @@ def lib():
         L.hlbm_set_fields.argtypes = [vp, vp, vp]
         L.hlbm_step.argtypes = [vp, i32]
         L.hlbm_set_fluid_accel.argtypes = [vp, vp]
+        L.hlbm_set_mesh.argtypes = [vp, vp, i32, vp, i32]
         L.hlbm_get_forces.argtypes = [vp, vp, vp, vp]
         L.hlbm_get_fields.argtypes = [vp, ctypes.c_uint32, vp, i32]
         L.hlbm_num_particles.argtypes = [vp, ctypes.POINTER(i32)]
@@ -118,7 +121,7 @@ def _check(rc):
 
 def make_config(n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps=0.5, rho_f=1.0,
                 gravity=(0.0, 0.0, 0.0), fluid_accel=(0.0, 0.0, 0.0), stream=None,
-                learned_max_circumradius=0.0, learned_samples=0):
+                learned_max_circumradius=0.0, learned_samples=0, max_mesh_triangles=0):
     c = hlbm_config()
     c.nx, c.ny, c.nz = (int(v) for v in n)
     c.bc = (ctypes.c_int32 * 3)(*[int(b) for b in bc])
@@ -131,6 +134,7 @@ def make_config(n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps
     c.learned = 1 if learned_max_circumradius > 0 else 0
     c.learned_samples = int(learned_samples)
     c.learned_max_circumradius = float(learned_max_circumradius)
+    c.max_mesh_triangles = int(max_mesh_triangles)
     return c
 
 
@@ -148,7 +152,7 @@ class Simulation:
 
     def __init__(self, n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps=0.5,
                  rho_f=1.0, gravity=(0.0, 0.0, 0.0), fluid_accel=(0.0, 0.0, 0.0), device=None,
-                 stream=None, learned_max_circumradius=0.0, learned_samples=0):
+                 stream=None, learned_max_circumradius=0.0, learned_samples=0, max_mesh_triangles=0):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -157,7 +161,7 @@ class Simulation:
         self.N = self.n[0] * self.n[1] * self.n[2]
         self.cfg = make_config(n, bc, tau, precision, max_particles, eps, rho_f, gravity,
                                fluid_accel, ctypes.c_void_p(self.stream.cuda_stream),
-                               learned_max_circumradius, learned_samples)
+                               learned_max_circumradius, learned_samples, max_mesh_triangles)
         nbytes = ctypes.c_size_t(0)
         _check(lib().hlbm_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
@@ -201,6 +205,13 @@ class Simulation:
         cnt = ctypes.c_int64(0)
         _check(lib().hlbm_profile_end(self._ctx, ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
+
+    def set_mesh(self, vertices, triangles):
+        """Closed triangle mesh of HLBM_MESH particles (unit scale, body frame,
+        counter-clockwise seen from outside)."""
+        v = np.ascontiguousarray(vertices, dtype=np.float32).reshape(-1, 3)
+        t = np.ascontiguousarray(triangles, dtype=np.int32).reshape(-1, 3)
+        _check(lib().hlbm_set_mesh(self._ctx, v.ctypes.data, len(v), t.ctypes.data, len(t)))
 
     def set_fluid_accel(self, accel):
         """Fluid body acceleration (outside the solid) from the next step on."""
