@@ -33,27 +33,32 @@ HBM_PEAK_GBS = 8000.0
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f32 (f16 storage)"}
 DEFAULT_PRECISION = {"spheres128": "fp32", "sphere32": "fp64", "mixed256": "fp16s",
-                     "mixed256_learned": "fp16s", "hindered384": "fp32", "hindered384b": "fp32"}
+                     "mixed256_learned": "fp16s", "hindered384": "fp32", "hindered384b": "fp32",
+                     "meshes128": "fp32", "meshes128_learned": "fp32"}
 # surrogate training settings for the learned-indicator workload
 TRAIN = dict(samples=1_000_000, holdout=100_000, iterations=30000, batch=8192, lr=1e-2, lr_final=1e-5,
              band=0.1, clip=0.25, band_share=0.8, gate_rms=0.05, gate_max=0.5)
 
 
 def make_sim(H, W, wl, precision):
-    """A context for the workload; for the learned workload the two
-    non-spherical families are trained first (outside any timed region)."""
+    """A context for the workload; for a learned workload the non-spherical
+    families present are trained first (outside any timed region)."""
     import numpy as np
     learned = bool(getattr(wl, "learned", False))
+    mesh = bool(len(wl.particles)) and bool(np.any(wl.particles["shape"] == W.MESH))
     rmax = 0.0
-    if learned:
+    if learned or mesh:
         rmax = max(W.circumradius(int(s), p) for s, p in zip(wl.particles["shape"], wl.particles["param"]))
     sim = H.Simulation(wl.n, wl.bc, wl.tau, precision, max_particles=len(wl.particles),
                        gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f,
-                       learned_max_circumradius=rmax + 0.01 if learned else 0.0,
-                       learned_samples=1_100_000 if learned else 0)
+                       learned_max_circumradius=rmax + 0.01 if (learned or mesh) else 0.0,
+                       learned_samples=1_100_000 if learned else 0,
+                       max_mesh_triangles=len(W.MESH_UNIT[1]) if mesh else 0)
+    if mesh:
+        sim.set_mesh(*W.MESH_UNIT)
     reports = {}
     if learned:
-        for s in (W.ROUNDED_CUBE, W.SPHEROID):
+        for s in (W.ROUNDED_CUBE, W.SPHEROID, W.MESH):
             sel = wl.particles["shape"] == s
             if not np.any(sel):
                 continue
@@ -100,8 +105,14 @@ def force_error_vs_fp64(H, wl, precision, steps, every):
     sums = {}
     for prec in (precision, "fp64"):
         if prec == "fp64":   # the FP64 plain form: exact indicator
+            mesh = bool(np.any(wl.particles["shape"] == W.MESH))
+            rmax = max(W.circumradius(int(s), p) for s, p in zip(wl.particles["shape"], wl.particles["param"]))
             sim = H.Simulation(wl.n, wl.bc, wl.tau, prec, max_particles=len(wl.particles),
-                               gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f)
+                               gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f,
+                               learned_max_circumradius=rmax + 0.01 if mesh else 0.0,
+                               max_mesh_triangles=len(W.MESH_UNIT[1]) if mesh else 0)
+            if mesh:
+                sim.set_mesh(*W.MESH_UNIT)
             sim.set_particles(wl.particles)
         else:
             sim, _ = make_sim(H, W, wl, prec)

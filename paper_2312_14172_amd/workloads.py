@@ -494,6 +494,21 @@ def small_spheres(n=128, count=4200, seed=11, tau=0.6, steps=100, precision="fp3
     return w
 
 
+def mesh_particles(n=128, count=100, r_eq=6.0, seed=13, tau=0.8, steps=1000, precision="fp32", learned=False):
+    """Triangle-mesh particles (the bumpy 320-triangle mesh MESH_UNIT) with
+    the volume of a sphere of radius r_eq, random orientations, RSA on
+    circumspheres (gap 2), z walls."""
+    rng = np.random.default_rng(seed)
+    s = equal_volume_params(MESH, r_eq)
+    rc = circumradius(MESH, s)
+    pos = rsa_positions(rng, np.full(count, rc), (n, n, n), (0, 0, 1), gap=2.0, wall_margin=2.0)
+    w = Workload(f"meshes{n}" + ("_learned" if learned else ""), (n, n, n), (0, 0, 1), tau, steps, precision,
+                 seed=seed, learned=learned,
+                 description=f"{n}^3, z walls, {count} meshes of {len(MESH_UNIT[1])} triangles, r_eq {r_eq}")
+    w.particles = np.array([make_particle(MESH, s, x, quat=shoemake_quaternion(rng)) for x in pos])
+    return w
+
+
 def get(name: str, **kw) -> Workload:
     """Named workloads:
     sphere32   -- 32^3 periodic, one sphere (parity case);
@@ -503,7 +518,9 @@ def get(name: str, **kw) -> Workload:
     hindered384 -- 384^3, z walls, 11 265 mixed shapes r_eq~U[4,8], tau 0.55;
     hindered384b -- as hindered384 with 20 000 particles, r_eq~U[3.30,6.61]
                   (the same solid fraction 0.2);
-    small4200  -- 128^3, z walls, 4200 spheres r~U[1.5,2.5] (parity case).
+    small4200  -- 128^3, z walls, 4200 spheres r~U[1.5,2.5] (parity case);
+    meshes128 / meshes128_learned -- 128^3, z walls, 100 triangle meshes
+                  (r_eq 6), exact distance / learned indicator.
     """
     if name == "sphere32":
         return single_sphere(**kw)
@@ -517,6 +534,10 @@ def get(name: str, **kw) -> Workload:
         return hindered_settling(**kw)
     if name == "hindered384b":
         return hindered_settling(count=20000, r_eq_range=(3.30, 6.61), name="hindered384b", **kw)
+    if name == "meshes128":
+        return mesh_particles(**kw)
+    if name == "meshes128_learned":
+        return mesh_particles(learned=True, **kw)
     if name == "small4200":
         return small_spheres(**kw)
     raise KeyError(name)
