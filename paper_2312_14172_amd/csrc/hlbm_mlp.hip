@@ -325,14 +325,24 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ theta
 }
 
 // Sum the workgroup partials in a fixed order; optionally apply one Adam step
-// (Kingma & Ba 2015, bias-corrected) to the FP32 master parameters.
-__global__ void k_mlp_reduce_adam(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
-                                  const float *__restrict__ partial, int nblocks, float *__restrict__ grad_out,
-                                  int do_step, float lr, float b1, float b2, float eps, float bc1, float bc2) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p > MLP_NPARAM) return;
-  float gsum = 0.f;
-  for (int b = 0; b < nblocks; ++b) gsum += partial[(size_t)b * MLP_PARTIAL + p];
+// (Kingma & Ba 2015, bias-corrected) to the FP32 master parameters.  One
+// workgroup per 64 parameters: wavefront w sums the partials w, w + 4, ...
+// of its lane's parameter, and the four wavefront sums are added in order.
+__global__ __launch_bounds__(256) void k_mlp_reduce_adam(float *__restrict__ theta, float *__restrict__ m,
+                                                         float *__restrict__ v, const float *__restrict__ partial,
+                                                         int nblocks, float *__restrict__ grad_out, int do_step,
+                                                         float lr, float b1, float b2, float eps, float bc1,
+                                                         float bc2) {
+  __shared__ float part[4][64];
+  const int lane = lane_id(), w = wave_id();
+  const int p = blockIdx.x * 64 + lane;
+  float gs = 0.f;
+  if (p <= MLP_NPARAM)
+    for (int b = w; b < nblocks; b += 4) gs += partial[(size_t)b * MLP_PARTIAL + p];
+  part[w][lane] = gs;
+  __syncthreads();
+  if (w != 0 || p > MLP_NPARAM) return;
+  const float gsum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
   if (grad_out) grad_out[p] = gsum;
   if (!do_step || p == MLP_NPARAM) return;
   const float mn = b1 * m[p] + (1.f - b1) * gsum;
@@ -537,7 +547,7 @@ hipError_t mlp_reduce_adam(float *theta, float *m, float *v, const float *partia
                            int do_step, float lr, int step, hipStream_t s) {
   const float b1 = 0.9f, b2 = 0.999f;
   const float bc1 = 1.f - powf(b1, (float)step), bc2 = 1.f - powf(b2, (float)step);
-  hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, theta, m, v, partial,
+  hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((MLP_NPARAM + 1 + 63) / 64), dim3(256), 0, s, theta, m, v, partial,
                      nblocks, grad_out, do_step, lr, b1, b2, 1e-8f, bc1, bc2);
   return hipGetLastError();
 }
