@@ -145,3 +145,36 @@ def test_learned_mesh_indicator_gains_over_exact(H):
     assert abs(le["B0"].sum() / ex["B0"].sum() - 1) <= 5e-3
     assert ferr <= 0.01
     assert gain >= 5.0
+
+
+def test_mesh_validation(H):
+    """hlbm_set_mesh rejects bad indices, too many triangles, a mesh wound the
+    wrong way (winding number -1 around the origin) and a mesh set after the
+    particles; mesh particles need a mesh."""
+    v, t = W.MESH_UNIT
+    sim = H.Simulation((32, 32, 32), (0, 0, 0), 0.8, "fp64", max_particles=2, max_mesh_triangles=len(t),
+                       learned_max_circumradius=6.0)
+    part = np.array([W.make_particle(W.MESH, W.equal_volume_params(W.MESH, 3.0), (16.0, 16.0, 16.0))])
+    with pytest.raises(H.HLBMError, match="no mesh"):
+        sim.set_particles(part)
+    bad = t.copy()
+    bad[3, 1] = len(v)
+    with pytest.raises(H.HLBMError, match="out of range"):
+        sim.set_mesh(v, bad)
+    with pytest.raises(H.HLBMError, match="winding"):
+        sim.set_mesh(v, t[:, ::-1])
+    big = np.concatenate([t, t[:1]])
+    with pytest.raises(H.HLBMError, match="max_mesh_triangles"):
+        sim.set_mesh(v, big)
+    sim.set_mesh(v, t)
+    sim.set_particles(part)
+    with pytest.raises(H.HLBMError, match="before the particles"):
+        sim.set_mesh(v, t)
+    sim.step(2)
+    F, T, st = sim.get_forces()
+    assert np.all(np.isfinite(F)) and np.all(np.isfinite(T))
+    # the library stored scale x (largest vertex radius, least surface distance)
+    s = part["param"][0, 0]
+    assert abs(st["param"][0, 1] - s * W.MESH_RC) < 1e-6 * s
+    assert 0.8 * s < st["param"][0, 2] < s
+    sim.close()
