@@ -8,8 +8,12 @@ What is checked:
   * at phi <= 0.1 it lies within [0.9, 1.15] of the Richardson-Zaki power
     law (measured +11 % / +12 % at N = 12; the paper reports agreement with
     the first two correlations at low phi);
-  * resolution: N = 12 and N = 18 agree within 2 % at phi = 0.1 (the paper's
-    grid study finds errors below 2 % from N = 12 on)."""
+  * resolution: N = 12 and N = 18 agree at phi = 0.1 within 2 % (the paper's
+    grid study finds errors below 2 % from N = 12 on) plus twice the
+    statistical error of the difference.  A single run is one realisation of
+    a chaotic suspension: a change in the last bit of the forces (another
+    floating-point contraction order) moved the N = 18 mean by 1.9 %, so the
+    time-average's standard error (batch means) is part of the bound."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -34,7 +38,7 @@ def _run(S, phi, N):
         print(f"settling: phi {phi}, N {N}", flush=True)
         _RUNS[key] = S.run_periodic(phi, N=N, seed=7, gap=1.0)
         r = _RUNS[key]
-        print(f"  u_bar/u* {r['ratio']:.4f}  RZ {r['rz']:.4f}  GAD {r['gad']:.4f}  BM {r['bm']:.4f}  "
+        print(f"  u_bar/u* {r['ratio']:.4f} +- {r['ratio_se']:.4f}  RZ {r['rz']:.4f}  GAD {r['gad']:.4f}  BM {r['bm']:.4f}  "
               f"flux {r['mean_flux']:.2e}  {r['seconds']:.1f} s", flush=True)
     return _RUNS[key]
 
@@ -52,4 +56,8 @@ def test_settling_velocity_against_correlations(S):
 
 def test_settling_resolution_independence(S):
     a, b = _run(S, 0.1, 12), _run(S, 0.1, 18)
-    assert abs(a["ratio"] - b["ratio"]) <= 0.02 * b["ratio"]
+    # standard errors measured: 0.0072 (N = 12) and 0.0037 (N = 18), so the
+    # bound is about 4 %; the means differ by 0.9 %
+    noise = 2.0 * (a["ratio_se"] ** 2 + b["ratio_se"] ** 2) ** 0.5
+    assert noise == noise and b["samples"] > 100
+    assert abs(a["ratio"] - b["ratio"]) <= 0.02 * b["ratio"] + noise
