@@ -40,8 +40,16 @@ __device__ inline double circumradius(int shape, double p0, double p1) {
 __device__ inline void cell_box(const Lattice &L, const double *X, double reach, int *lo, int *hi) {
   const int n[3] = {L.nx, L.ny, L.nz};
   for (int k = 0; k < 3; ++k) {
-    int a = (int)ceil(X[k] - reach - 0.5);
-    int b = (int)floor(X[k] + reach - 0.5);
+    const double fa = ceil(X[k] - reach - 0.5), fb = floor(X[k] + reach - 0.5);
+    if (!(fa > -1e9 && fb < 1e9)) {
+      // a non-finite or runaway centre (a diverged run, already flagged in
+      // the status word): an empty box instead of an unbounded cell range
+      lo[k] = 0;
+      hi[k] = -1;
+      continue;
+    }
+    int a = (int)fa;
+    int b = (int)fb;
     if (L.bc[k]) {
       a = max(a, 0);
       b = min(b, n[k] - 1);
@@ -240,6 +248,12 @@ __device__ inline void advance_particle(const Lattice &L, DevParticle &p, const 
       if (!L.bc[k]) {
         if (p.X[k] >= nn[k]) p.X[k] -= nn[k];
         else if (p.X[k] < 0.0) p.X[k] += nn[k];
+        if (!(p.X[k] >= 0.0 && p.X[k] < nn[k])) {
+          // moved a lattice length or more in one step, or non-finite: the
+          // run has diverged; keep the centre inside the lattice
+          atomicOr(status, ST_UNSTABLE);
+          p.X[k] = 0.5 * nn[k];
+        }
       } else if (!(p.X[k] >= 0.0 && p.X[k] <= nn[k])) {
         atomicOr(status, ST_WALL_EXIT);
       }
