@@ -515,6 +515,67 @@ void orc_apply_eom(const ocfg *cfg, int np, opart *P, const double *F, const dou
 }
 
 /* ---------------------------------------------------------------------------
+ * Contact between spheres (an addition: the paper runs without a contact
+ * model and names one only by citation, Sec. 2.2 and Sec. 5.2).
+ * reading: the short-range repulsion of Glowinski, Pan, Hesla, Joseph and
+ * Periaux (J. Comput. Phys. 169, 2001).  Two spheres whose centres are closer
+ * than R_p + R_q + zeta repel along the line of centres with
+ *     F_pq = k ((R_p + R_q + zeta - d) / zeta)^2 (X_p - X_q) / d,
+ * and a wall acts on a sphere like its mirror image (centre distance
+ * d' = 2 h, h the distance of the centre from the wall):
+ *     F_pw = k_w ((2 R_p + zeta - d') / zeta)^2, directed away from the wall.
+ * Only sphere pairs take part; separations are minimum images on periodic
+ * axes; the state is that of time t (the one the momentum exchange reads), and
+ * the force is added to the hydrodynamic force in the equations of motion.
+ * Sums run over q = 0, 1, ..., np-1, then the walls axis by axis (lower wall
+ * first).
+ * ------------------------------------------------------------------------- */
+static double g_contact_range = 0.0, g_contact_k = 0.0, g_contact_kw = 0.0;
+
+void orc_set_contact(double range, double k, double kw) {
+    g_contact_range = range;
+    g_contact_k = k;
+    g_contact_kw = kw;
+}
+
+void orc_contact_forces(const ocfg *cfg, int np, const opart *P, double range, double k, double kw,
+                        double *Fc) {
+    for (int p = 0; p < np; ++p) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        if (P[p].shape == SH_SPHERE && range > 0.0) {
+            const double Rp = P[p].prm[0];
+            for (int q = 0; q < np; ++q) {
+                if (q == p || P[q].shape != SH_SPHERE) continue;
+                double dx[3];
+                for (int a = 0; a < 3; ++a) {
+                    dx[a] = P[p].X[a] - P[q].X[a];
+                    if (cfg->bc[a] == 0) dx[a] -= cfg->n[a] * round(dx[a] / cfg->n[a]);
+                }
+                const double d = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+                const double reach = Rp + P[q].prm[0] + range;
+                if (!(d < reach) || d == 0.0) continue;
+                const double s = (reach - d) / range;
+                for (int a = 0; a < 3; ++a) acc[a] += k * s * s * dx[a] / d;
+            }
+            for (int a = 0; a < 3; ++a) {
+                if (cfg->bc[a] == 0) continue;
+                const double dlo = 2.0 * P[p].X[a], dhi = 2.0 * (cfg->n[a] - P[p].X[a]);
+                const double reach = 2.0 * Rp + range;
+                if (dlo < reach) {
+                    const double s = (reach - dlo) / range;
+                    acc[a] += kw * s * s;
+                }
+                if (dhi < reach) {
+                    const double s = (reach - dhi) / range;
+                    acc[a] -= kw * s * s;
+                }
+            }
+        }
+        for (int a = 0; a < 3; ++a) Fc[3 * p + a] = acc[a];
+    }
+}
+
+/* ---------------------------------------------------------------------------
  * Particle -> lattice: indicator and solid velocity fields (Sec. 3.2).
  * reading (overlap of smoothed regions, not covered by the paper):
  *   S0 = sum_p B_p, S1 = sum_p B_p u_p(x); B = min(1, S0), u_s = S1 / S0.
@@ -557,8 +618,8 @@ void orc_coupling(const ocfg *cfg, int np, const opart *P, double *B, double *us
 
 /* ---------------------------------------------------------------------------
  * One time step in the order of the paper's time-step algorithm (Sec. 4.2):
- * MEA -> external force -> equations of motion -> EDM coupling -> collide ->
- * stream.  The communication and assignment steps have nothing to do on one
+ * MEA -> external force (and contact, when set) -> equations of motion ->
+ * EDM coupling -> collide -> stream.  The communication and assignment steps have nothing to do on one
  * address space.  F_last/T_last receive the hydrodynamic force and torque of
  * the last MEA.  Returns 0.
  * ------------------------------------------------------------------------- */
@@ -570,16 +631,26 @@ int orc_run(const ocfg *cfg, int np, opart *P, double *f, int nsteps, double *Fl
     double *us = (double *)malloc(sizeof(double) * 3 * (size_t)N);
     double *F = (double *)calloc((size_t)(np > 0 ? np : 1) * 3, sizeof(double));
     double *T = (double *)calloc((size_t)(np > 0 ? np : 1) * 3, sizeof(double));
+    double *Fc = (double *)calloc((size_t)(np > 0 ? np : 1) * 3, sizeof(double));
+    const int contact = g_contact_range > 0.0 && (g_contact_k != 0.0 || g_contact_kw != 0.0);
     for (int s = 0; s < nsteps; ++s) {
         orc_mea(cfg, np, P, f, F, T);
-        orc_apply_eom(cfg, np, P, F, T);
+        if (contact) {
+            /* the equations of motion take F + F_contact; F stays the
+             * hydrodynamic force that is reported */
+            orc_contact_forces(cfg, np, P, g_contact_range, g_contact_k, g_contact_kw, Fc);
+            for (int i = 0; i < 3 * np; ++i) Fc[i] = F[i] + Fc[i];
+            orc_apply_eom(cfg, np, P, Fc, T);
+        } else {
+            orc_apply_eom(cfg, np, P, F, T);
+        }
         orc_coupling(cfg, np, P, B, us);
         orc_collide(cfg, f, B, us, fs);
         orc_stream(cfg, fs, f);
     }
     if (Flast && nsteps > 0) memcpy(Flast, F, sizeof(double) * 3 * np);
     if (Tlast && nsteps > 0) memcpy(Tlast, T, sizeof(double) * 3 * np);
-    free(fs); free(B); free(us); free(F); free(T);
+    free(fs); free(B); free(us); free(F); free(T); free(Fc);
     return 0;
 }
 

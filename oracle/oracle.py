@@ -62,6 +62,9 @@ def lib():
         L.orc_sdf.argtypes = [ctypes.c_int, dp, dp]
         L.orc_sdf.restype = ctypes.c_double
         L.orc_set_mesh.argtypes = [dp, ctypes.c_int]
+        L.orc_set_contact.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_contact_forces.argtypes = [cp, ctypes.c_int, vp, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, dp]
         L.orc_circumradius.argtypes = [ctypes.c_int, dp]
         L.orc_circumradius.restype = ctypes.c_double
         L.orc_indicator.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -91,7 +94,10 @@ class Oracle:
     """A lattice configuration plus the oracle's passes over numpy arrays."""
 
     def __init__(self, n, bc=(0, 0, 0), tau=0.8, eps=0.5, rho_f=1.0, gravity=(0.0, 0.0, 0.0),
-                 fluid_accel=(0.0, 0.0, 0.0)):
+                 fluid_accel=(0.0, 0.0, 0.0), contact=None):
+        # contact: None, or (range zeta, stiffness k, wall stiffness k_w) of the
+        # sphere repulsion added to the equations of motion
+        self.contact = tuple(float(v) for v in contact) if contact else (0.0, 0.0, 0.0)
         self.n = tuple(int(v) for v in n)
         self.bc = tuple(int(v) for v in bc)
         self.cfg = OCfg((ctypes.c_int * 3)(*self.n), (ctypes.c_int * 3)(*self.bc), float(tau),
@@ -234,9 +240,19 @@ class Oracle:
         """Advance f and P in place by nsteps; returns the last MEA force/torque."""
         F = np.zeros((max(len(P), 1), 3))
         T = np.zeros((max(len(P), 1), 3))
+        lib().orc_set_contact(*self.contact)
         lib().orc_run(ctypes.byref(self.cfg), len(P), P.ctypes.data if len(P) else None, _dp(f),
                       int(nsteps), F.ctypes.data, T.ctypes.data)
         return F[:len(P)], T[:len(P)]
+
+    def contact_forces(self, P, contact=None):
+        """Sphere contact forces [np, 3] on the state P (the repulsion the
+        equations of motion add when contact is set)."""
+        rng, k, kw = (float(v) for v in (contact or self.contact))
+        Fc = np.zeros((max(len(P), 1), 3))
+        lib().orc_contact_forces(ctypes.byref(self.cfg), len(P), P.ctypes.data if len(P) else None, rng, k, kw,
+                                 _dp(Fc))
+        return Fc[:len(P)]
 
     def fields(self, P, f):
         rho = np.zeros(self.N)
