@@ -181,6 +181,23 @@ int hlbm_set_mesh(hlbm_ctx *ctx, const float *vertices, int32_t nv, const int32_
  * with HLBM_EINVAL and leave the acceleration unchanged. */
 int hlbm_set_fluid_accel(hlbm_ctx *ctx, const double accel[3]);
 
+/* Sphere contact, off by default.  Sec. 2.2 lets contact forces enter the
+ * particles' equations of motion next to the hydrodynamic ones and Sec. 5.2
+ * names the missing contact model as the likely cause of the overestimated
+ * settling velocities at high volume fractions, without giving a model.
+ * This is the short-range repulsion of Glowinski et al. (J. Comput. Phys.
+ * 169, 2001): spheres whose centres are closer than R_p + R_q + range repel
+ * along the line of centres with stiffness * ((R_p + R_q + range - d) /
+ * range)^2 (minimum image on periodic axes), and a wall pushes a sphere whose
+ * centre is at distance h with wall_stiffness * ((2 R + range - 2 h) /
+ * range)^2 (its mirror image).  Only spheres take part; the force acts on the
+ * state of the step's momentum exchange and is added to the hydrodynamic
+ * force in the equations of motion (hlbm_get_forces still reports the
+ * hydrodynamic force alone).  All n^2 pairs are tested every step.
+ * Stream-ordered like hlbm_set_fluid_accel; range = 0 or both stiffnesses 0
+ * turn it off.  HLBM_EINVAL for negative or non-finite values. */
+int hlbm_set_contact(hlbm_ctx *ctx, double range, double stiffness, double wall_stiffness);
+
 /* Copy to host the hydrodynamic force F[n][3] and torque T[n][3] on each
  * particle from the last completed step's momentum exchange (zero before the
  * first step), and optionally the current particle records.  Any pointer may

@@ -48,7 +48,7 @@ constexpr int MEA_CHUNKED_MIN = 4096;
 size_t pop_bytes(int precision) { return precision == HLBM_FP64 ? 8 : (precision == HLBM_FP32 ? 4 : 2); }
 
 struct Layout {
-  size_t fA, fB, parts, order, stage_parts, tcnt[2], tlist[2], partial, status, stage, total;
+  size_t fA, fB, parts, order, stage_parts, tcnt[2], tlist[2], partial, contact, status, stage, total;
   // learned indicator (cfg.learned)
   size_t theta[NFAM], mom1[NFAM], mom2[NFAM], packed[NFAM], gpart, gout, pool, epts, eout, tables, mesh;
   long long pool_cap, table_cap;
@@ -114,6 +114,7 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
     y.tlist[b] = off; off += align_up((size_t)L.ntiles * MAXC * sizeof(int));
   }
   y.partial = off; off += align_up(np * LMAX_CAP * 6 * sizeof(double));
+  y.contact = off; off += align_up(np * (size_t)contact_chunks((int)np) * 3 * sizeof(double));
   y.status = off; off += 256;
   y.stage = off; off += align_up((size_t)4 * L.N * sizeof(double));
   y.mesh = off; off += align_up((size_t)(c->max_mesh_triangles > 0 ? c->max_mesh_triangles : 1) * 3 * sizeof(float4));
@@ -159,6 +160,8 @@ struct hlbm_ctx {
   int *tcnt[2], *tlist[2], *status;
   int cur;            // tile-list buffer describing the current particles
   double *partial, *stage;
+  double *contact;    // per-chunk sphere contact forces [chunk][n][3]
+  ContactParams cparams;
   int lmax;           // z-layers of the largest momentum-exchange box
   int n;
   int bin_cap;        // tiles a particle's coupling box can touch (bin grid width)
@@ -289,6 +292,8 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   }
   c->cur = 0;
   c->partial = (double *)(c->base + lay.partial);
+  c->contact = (double *)(c->base + lay.contact);
+  c->cparams = ContactParams{0.0, 0.0, 0.0, 0};
   c->lmax = 1;
   c->status = (int *)(c->base + lay.status);
   c->stage = (double *)(c->base + lay.stage);
@@ -538,8 +543,9 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
       // enough workgroups to fill the chip, few enough to amortise each)
       const int layers = ctx->n >= 1000 ? 4 : 2;
       HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers, ctx->mea_chunked, ctx->partial, s));
-      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, layers, ctx->partial, ctx->tcnt[nxt],
-                             ctx->tlist[nxt], ctx->status, s));
+      HIP_TRY(launch_contact(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->contact, s));
+      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, layers, ctx->partial, ctx->cparams,
+                             ctx->contact, ctx->tcnt[nxt], ctx->tlist[nxt], ctx->status, s));
       int rc = refresh_tables(ctx);
       if (rc) return rc;
     }
@@ -653,6 +659,18 @@ int hlbm_set_fluid_accel(hlbm_ctx *ctx, const double accel[3]) {
     ctx->cfg.fluid_accel[k] = accel[k];
     ctx->L.af[k] = accel[k];
   }
+  return HLBM_OK;
+}
+
+int hlbm_set_contact(hlbm_ctx *ctx, double range, double stiffness, double wall_stiffness) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  if (!(isfinite(range) && isfinite(stiffness) && isfinite(wall_stiffness)))
+    return fail(HLBM_EINVAL, "contact parameters not finite");
+  if (range < 0.0 || stiffness < 0.0 || wall_stiffness < 0.0)
+    return fail(HLBM_EINVAL, "contact range and stiffnesses must be >= 0");
+  // passed by value at each launch: applies from the next queued step on
+  ctx->cparams = ContactParams{range, stiffness, wall_stiffness,
+                               range > 0.0 && (stiffness > 0.0 || wall_stiffness > 0.0) ? 1 : 0};
   return HLBM_OK;
 }
 

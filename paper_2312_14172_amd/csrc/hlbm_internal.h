@@ -29,8 +29,23 @@ hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int cap
                       int *status, hipStream_t s);
 hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevParticle *parts, const int *order, int n,
                       int lmax, int layers, int chunked, double *partial, hipStream_t s);
+// sphere contact: short-range repulsion of range `range`, pair stiffness k,
+// wall stiffness kw (on = range > 0 and k or kw nonzero)
+struct ContactParams {
+  double range, k, kw;
+  int on;
+};
+constexpr int CONTACT_TILE = 1024;      // partners staged in LDS at a time
+constexpr int CONTACT_MAX_CHUNKS = 64;  // partner chunks = partial sums per particle
+__host__ __device__ inline int contact_chunks(int n) {
+  return n < 1 ? 1 : (n > CONTACT_MAX_CHUNKS ? CONTACT_MAX_CHUNKS : n);
+}
+// per-chunk contact forces out[chunk][n][3] from the state before the EoM
+hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c, double *out,
+                          hipStream_t s);
 hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, const double *partial,
-                          int *tcnt, int *tlist, int *status, hipStream_t s);
+                          const ContactParams &c, const double *contact, int *tcnt, int *tlist, int *status,
+                          hipStream_t s);
 hipError_t launch_collide(int prec, const Lattice &L, const void *A, void *B, const DevParticle *parts,
                           const int *tcnt, const int *tlist, int *tcnt_clear, int *status, hipStream_t s);
 hipError_t launch_set_fields(int prec, const Lattice &L, void *A, const double *rho, const double *u,

@@ -10,7 +10,9 @@
 //   k_eom_bin  one workgroup per particle: the slab records summed in a fixed
 //              order, gravity and buoyancy, Newton-Euler and quaternion update
 //              in FP64, then the particle appended to the tile lists of its new
-//              coupling box (tiles of 64 x 4 x 4 cells).
+//              coupling box (tiles of 64 x 4 x 4 cells);
+//   k_contact  (only with contact set) pairwise sphere repulsion, launched
+//              between the two and summed into the force by k_eom_bin.
 #include "hlbm_device.h"
 #include "hlbm_internal.h"
 
@@ -232,18 +234,21 @@ __device__ inline void mea_accumulate(const Lattice &L, const typename ST::S *__
 }
 
 // Equations of motion of one particle in FP64 with dt = 1 (Sec. 2.2; Sec. 5.1
-// for the external force), from its hydrodynamic force and torque Fs:
+// for the external force), from its hydrodynamic force and torque Fs (plus
+// the contact force Fc when given; Fh and Th record Fs alone):
 //   U <- U + (F + (m - rho_f V) g) / m;  X <- X + U (wrapped on periodic axes);
 //   w_b <- w_b + I^-1 (T_b - w_b x I w_b) in the body frame;
 //   q <- normalize(q (x) exp(w_b / 2));  w <- R(q) w_b;
 // and the new coupling box.  Particles with m <= 0 are held fixed.
-__device__ inline void advance_particle(const Lattice &L, DevParticle &p, const double *Fs, int *status) {
+__device__ inline void advance_particle(const Lattice &L, DevParticle &p, const double *Fs, const double *Fc,
+                                        int *status) {
   const int nn[3] = {L.nx, L.ny, L.nz};
   for (int k = 0; k < 3; ++k) { p.Fh[k] = Fs[k]; p.Th[k] = Fs[3 + k]; }
   if (p.m > 0.0) {
     const double buoy = p.m - L.rho_f * p.V;
     for (int k = 0; k < 3; ++k) {
-      p.U[k] += (Fs[k] + buoy * L.g[k]) / p.m;
+      const double Fk = Fc ? Fs[k] + Fc[k] : Fs[k];
+      p.U[k] += (Fk + buoy * L.g[k]) / p.m;
       p.X[k] += p.U[k];
       if (!L.bc[k]) {
         if (p.X[k] >= nn[k]) p.X[k] -= nn[k];
@@ -421,13 +426,89 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST::kind ==
   if (t < 6) partial[((size_t)pid * lmax + slab) * 6 + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
 }
 
+// Sphere contact (an addition: the paper runs without a contact model and
+// cites one, Sec. 2.2 and 5.2): the short-range repulsion of Glowinski et al.
+// (J. Comput. Phys. 169, 2001).  Spheres p and q with centre distance
+// d < R_p + R_q + range (minimum image on periodic axes) repel along the line
+// of centres with k ((R_p + R_q + range - d) / range)^2.  Workgroup (bp, c)
+// takes 256 particles p and the c-th of up to 64 contiguous chunks of
+// partners q (enough workgroups to fill the chip for a few hundred
+// particles), staged in LDS 1024 at a time as (X, R) with R < 0 for other
+// shapes; each thread sums its chunk in increasing q into out[c][p].  O(n^2)
+// pair tests without a neighbour structure; a pair out of range costs a
+// squared distance and one compare.
+__global__ __launch_bounds__(256) void k_contact(Lattice L, const DevParticle *__restrict__ parts, int n,
+                                                 ContactParams c, double *__restrict__ out) {
+  __shared__ double4 sq[CONTACT_TILE];
+  const int nchunk = gridDim.y;
+  const int per = (n + nchunk - 1) / nchunk;
+  const int q_begin = blockIdx.y * per, q_end = min(n, q_begin + per);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nn[3] = {L.nx, L.ny, L.nz};
+  double Xp[3] = {0, 0, 0}, Rp = -1.0;
+  if (p < n && parts[p].shape == 0) {
+    for (int a = 0; a < 3; ++a) Xp[a] = parts[p].X[a];
+    Rp = parts[p].prm[0];
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int t0 = q_begin; t0 < q_end; t0 += CONTACT_TILE) {
+    const int nt = min(CONTACT_TILE, q_end - t0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < nt; j += blockDim.x) {
+      const DevParticle &q = parts[t0 + j];
+      sq[j] = make_double4(q.X[0], q.X[1], q.X[2], q.shape == 0 ? q.prm[0] : -1.0);
+    }
+    __syncthreads();
+    if (Rp > 0.0) {
+      for (int j = 0; j < nt; ++j) {
+        const double4 v = sq[j];
+        if (t0 + j == p || v.w < 0.0) continue;
+        double dx[3] = {Xp[0] - v.x, Xp[1] - v.y, Xp[2] - v.z};
+        for (int a = 0; a < 3; ++a)  // minimum image (centres lie in [0, n) on periodic axes)
+          if (!L.bc[a]) dx[a] = dx[a] > 0.5 * nn[a] ? dx[a] - nn[a] : (dx[a] < -0.5 * nn[a] ? dx[a] + nn[a] : dx[a]);
+        const double reach = Rp + v.w + c.range;
+        const double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
+        if (!(d2 < reach * reach) || d2 == 0.0) continue;
+        const double d = sqrt(d2);
+        const double sc = (reach - d) / c.range;
+        for (int a = 0; a < 3; ++a) acc[a] += c.k * sc * sc * dx[a] / d;
+      }
+    }
+  }
+  if (p < n)
+    for (int a = 0; a < 3; ++a) out[((size_t)blockIdx.y * n + p) * 3 + a] = acc[a];
+}
+
+// Wall part of the contact force on sphere p, added to Fc: each wall acts as
+// the mirror image (centre distance 2 h from the image; pushes away from the
+// wall with kw ((2 R + range - 2 h) / range)^2), axis by axis, lower wall
+// first.
+__device__ inline void contact_walls(const Lattice &L, const DevParticle &p, const ContactParams &c, double *Fc) {
+  if (p.shape != 0) return;
+  const int nn[3] = {L.nx, L.ny, L.nz};
+  const double reach = 2.0 * p.prm[0] + c.range;
+  for (int a = 0; a < 3; ++a) {
+    if (!L.bc[a]) continue;
+    const double dlo = 2.0 * p.X[a], dhi = 2.0 * (nn[a] - p.X[a]);
+    if (dlo < reach) {
+      const double sc = (reach - dlo) / c.range;
+      Fc[a] += c.kw * sc * sc;
+    }
+    if (dhi < reach) {
+      const double sc = (reach - dhi) / c.range;
+      Fc[a] -= c.kw * sc * sc;
+    }
+  }
+}
+
 // One 64-thread workgroup per particle: the slab records of k_mea summed in a
 // fixed order (thread t takes slabs t, t + 64, ..., then a fixed wavefront
 // butterfly), the equations of motion, then the particle appended to the tile
 // lists of its new coupling box.
-__global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restrict__ parts, int lmax,
-                                                int layers, const double *__restrict__ partial, int *tcnt,
-                                                int *tlist, int *status) {
+__global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restrict__ parts, int n, int lmax,
+                                                int layers, const double *__restrict__ partial, ContactParams c,
+                                                const double *__restrict__ contact, int *tcnt, int *tlist,
+                                                int *status) {
   __shared__ int ts[3][MAX_AXIS_TILES];
   __shared__ int tn[3];
   const int pid = blockIdx.x;
@@ -441,6 +522,10 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
   const bool have = t < nmax;
   if (have)
     for (int k = 0; k < 6; ++k) first[k] = src[t * 6 + k];
+  // contact: lane b holds chunk b's sum, reduced by the fixed wavefront tree
+  double fc[3] = {0.0, 0.0, 0.0};
+  if (c.on && t < contact_chunks(n))
+    for (int a = 0; a < 3; ++a) fc[a] = contact[((size_t)t * n + pid) * 3 + a];
   int lo[3], hi[3];
   cell_box(L, parts[pid].X, parts[pid].rc + 1e-9, lo, hi);
   const int nrec = mea_slabs(lo[2], hi[2], layers);
@@ -449,9 +534,16 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
   for (int r = t + 64; r < nrec; r += 64)
     for (int k = 0; k < 6; ++k) acc[k] += src[r * 6 + k];
   for (int k = 0; k < 6; ++k) acc[k] = wave_sum(acc[k]);
+  if (c.on)
+    for (int a = 0; a < 3; ++a) fc[a] = wave_sum(fc[a]);
   if (t == 0) {
     DevParticle p = parts[pid];
-    advance_particle(L, p, acc, status);
+    if (c.on) {
+      contact_walls(L, p, c, fc);
+      advance_particle(L, p, acc, fc, status);
+    } else {
+      advance_particle(L, p, acc, nullptr, status);
+    }
     parts[pid] = p;
     tn[0] = axis_tiles(p.lo[0], p.hi[0], L.nx, !L.bc[0], TX, ts[0]);
     tn[1] = axis_tiles(p.lo[1], p.hi[1], L.ny, !L.bc[1], TY, ts[1]);
@@ -518,10 +610,20 @@ hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevPartic
   return hipGetLastError();
 }
 
+hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c, double *out,
+                          hipStream_t s) {
+  if (n <= 0 || !c.on) return hipSuccess;
+  const dim3 grid(blocks_for(n, 256), contact_chunks(n));
+  hipLaunchKernelGGL(k_contact, grid, dim3(256), 0, s, L, parts, n, c, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, const double *partial,
-                          int *tcnt, int *tlist, int *status, hipStream_t s) {
+                          const ContactParams &c, const double *contact, int *tcnt, int *tlist, int *status,
+                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eom_bin, dim3(n), dim3(64), 0, s, L, parts, lmax, layers, partial, tcnt, tlist, status);
+  hipLaunchKernelGGL(k_eom_bin, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, partial, c, contact, tcnt, tlist,
+                     status);
   return hipGetLastError();
 }
 

@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 FIELD_RHO, FIELD_U, FIELD_U_PHYS, FIELD_SOLID = 1, 2, 4, 8
 
 EXPORTED = ["hlbm_workspace_size", "hlbm_init", "hlbm_destroy", "hlbm_set_particles",
-            "hlbm_set_fields", "hlbm_step", "hlbm_set_fluid_accel", "hlbm_set_mesh", "hlbm_get_forces",
+            "hlbm_set_fields", "hlbm_step", "hlbm_set_fluid_accel", "hlbm_set_contact", "hlbm_set_mesh",
+            "hlbm_get_forces",
             "hlbm_get_fields",
             "hlbm_num_particles", "hlbm_profile_begin", "hlbm_profile_end", "hlbm_mlp_set_params",
             "hlbm_mlp_get_params", "hlbm_mlp_eval", "hlbm_mlp_gradient", "hlbm_train_indicator",
@@ -92,6 +93,7 @@ def lib():
         L.hlbm_set_fields.argtypes = [vp, vp, vp]
         L.hlbm_step.argtypes = [vp, i32]
         L.hlbm_set_fluid_accel.argtypes = [vp, vp]
+        L.hlbm_set_contact.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.hlbm_set_mesh.argtypes = [vp, vp, i32, vp, i32]
         L.hlbm_get_forces.argtypes = [vp, vp, vp, vp]
         L.hlbm_get_fields.argtypes = [vp, ctypes.c_uint32, vp, i32]
@@ -217,6 +219,11 @@ class Simulation:
         """Fluid body acceleration (outside the solid) from the next step on."""
         a = np.ascontiguousarray(accel, dtype=np.float64).reshape(3)
         _check(lib().hlbm_set_fluid_accel(self._ctx, a.ctypes.data))
+
+    def set_contact(self, range_, stiffness, wall_stiffness=0.0):
+        """Sphere repulsion (range, pair stiffness, wall stiffness) from the
+        next step on; range 0 turns it off."""
+        _check(lib().hlbm_set_contact(self._ctx, float(range_), float(stiffness), float(wall_stiffness)))
 
     def get_forces(self):
         n = self.num_particles

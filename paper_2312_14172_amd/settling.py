@@ -99,12 +99,16 @@ def place_spheres(phi, N, seed, gap):
 
 
 def run_periodic(phi, N=12, Ar=1500.0, ratio=1.3, tau=0.55, t_total=300.0, t_avg=30.0, precision="fp32",
-                 seed=7, gap=1.0, control_every=20, sample_every=None, log=None):
+                 seed=7, gap=1.0, control_every=20, sample_every=None, log=None, contact=None):
     """Settle the suspension for t_total t* and average the settling velocity
     from t_avg t* on.  Returns the set-up, u_bar / u*, its standard error (from
     the means of 10 consecutive batches of samples, which are far less
     correlated than single samples), the three correlations, the residual
-    volume flux and the wall time."""
+    volume flux and the wall time.
+
+    contact = (range, factor) turns on the sphere repulsion of the library
+    (hlbm_set_contact) with that range in cells and a stiffness of `factor`
+    times one sphere's submerged weight (the force at touching)."""
     import torch
     s = setup(Ar, ratio, tau, N)
     L, pos = place_spheres(phi, N, seed, gap)
@@ -118,6 +122,9 @@ def run_periodic(phi, N=12, Ar=1500.0, ratio=1.3, tau=0.55, t_total=300.0, t_avg
     sim = H.Simulation((L, L, L), (0, 0, 0), tau, precision, max_particles=count, gravity=(0.0, 0.0, -g),
                        fluid_accel=(0.0, 0.0, a0))
     sim.set_particles(recs)
+    if contact:
+        weight = (ratio - 1.0) * g * math.pi * N ** 3 / 6.0
+        sim.set_contact(float(contact[0]), float(contact[1]) * weight, 0.0)
     nsteps = int(round(t_total * s["t_star"]))
     n_avg = int(round(t_avg * s["t_star"]))
     sample_every = sample_every or max(control_every, int(round(s["t_star"] / 2)) // control_every * control_every)
@@ -175,14 +182,17 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--gap", type=float, default=None, help="RSA surface gap (default 1, 0.2 from phi 0.25)")
+    ap.add_argument("--contact", type=float, nargs=2, default=None, metavar=("RANGE", "FACTOR"),
+                    help="sphere repulsion: range in cells, stiffness in submerged weights")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     H.lib()
     for phi in a.phi:
         gap = a.gap if a.gap is not None else (1.0 if phi < 0.25 else 0.2)
         r = run_periodic(phi, N=a.N, t_total=a.t_total, t_avg=a.t_avg, precision=a.precision, seed=a.seed,
-                         gap=gap, log=lambda m: print(m, flush=True))
+                         gap=gap, log=lambda m: print(m, flush=True), contact=a.contact)
         r["N"] = a.N
+        r["contact"] = a.contact
         print(json.dumps({k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}), flush=True)
 
 

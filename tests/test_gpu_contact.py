@@ -1,0 +1,135 @@
+"""Sphere contact on the GPU (the short-range repulsion of Glowinski et al.
+2001 that hlbm_set_contact adds to the equations of motion) against the
+oracle, through the C ABI.
+
+Tolerances of the FP64 parity cases as in test_gpu_parity.py; the contact
+force enters the particle velocities, so positions and velocities are
+compared as well as the hydrodynamic force."""
+import numpy as np
+import pytest
+
+from paper_2312_14172_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_14172_amd import hlbm
+    hlbm.lib()
+    return hlbm
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _cluster():
+    """Spheres in and out of contact range, one near the bottom wall, a pair
+    across the periodic x boundary, and a rounded cube (no contact) touching a
+    sphere; all moving."""
+    recs = [
+        W.make_particle(W.SPHERE, (3.0,), (12.3, 14.1, 15.2), vel=(0.004, 0.0, -0.002), omega=(0.0, 0.001, 0.0)),
+        W.make_particle(W.SPHERE, (2.5,), (17.6, 15.0, 14.7), vel=(-0.003, 0.001, 0.0)),
+        W.make_particle(W.SPHERE, (2.0,), (9.1, 19.2, 16.0)),
+        W.make_particle(W.SPHERE, (2.5,), (22.4, 8.3, 3.3), vel=(0.0, 0.0, -0.002)),
+        W.make_particle(W.SPHERE, (2.0,), (1.2, 24.0, 20.3), vel=(-0.002, 0.0, 0.0)),
+        W.make_particle(W.SPHERE, (2.2,), (37.4, 24.6, 20.0), vel=(0.003, 0.0, 0.0)),
+        W.make_particle(W.ROUNDED_CUBE, (2.6, 0.5), (12.0, 8.2, 15.5), vel=(0.0, 0.002, 0.0)),
+    ]
+    return np.array(recs)
+
+
+def _gpu(H, n, bc, parts, steps, contact, split=None):
+    sim = H.Simulation(n, bc, 0.8, "fp64", max_particles=len(parts), gravity=(0.0, 0.0, -2e-5))
+    sim.set_particles(parts)
+    if contact:
+        sim.set_contact(*contact)
+    for s in (split or (steps,)):
+        sim.step(s)
+    F, T, st = sim.get_forces()
+    fl = sim.get_fields()
+    sim.close()
+    return F, T, st, fl
+
+
+def test_contact_matches_oracle_fp64(H, oracle_mod):
+    n, bc = (40, 32, 36), (0, 0, 1)
+    parts = _cluster()
+    contact = (2.0, 4e-3, 1e-2)
+    _log("gpu: sphere contact cluster, 30 steps FP64")
+    F, T, st, fl = _gpu(H, n, bc, parts, 30, contact, split=(1, 14, 15))
+    orc = oracle_mod.Oracle(n, bc, 0.8, gravity=(0.0, 0.0, -2e-5), contact=contact)
+    P = orc.to_parts(parts)
+    Fc0 = orc.contact_forces(P)
+    f = orc.equilibrium()
+    Fo, To = orc.run(P, f, 30)
+    rho_o, u_o, _, B_o = orc.fields(P, f)
+    plain = oracle_mod.Oracle(n, bc, 0.8, gravity=(0.0, 0.0, -2e-5))
+    P2 = plain.to_parts(parts)
+    plain.run(P2, plain.equilibrium(), 30)
+    effect = np.abs(P["U"] - P2["U"]).max()
+    _log(f"  contact moved U by {effect:.3e};  max |dU| gpu-oracle {np.abs(st['vel'] - P['U']).max():.3e}")
+    assert np.count_nonzero(np.abs(Fc0).sum(1)) >= 5 and np.all(Fc0[6] == 0.0)
+    assert effect > 1e-4
+    np.testing.assert_allclose(st["vel"], P["U"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(st["pos"], P["X"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(st["omega"], P["W"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-10 * np.max(np.abs(Fo)))
+    np.testing.assert_allclose(T, To, rtol=0, atol=1e-9 * np.max(np.abs(To)))
+    np.testing.assert_allclose(fl["B"], B_o, rtol=0, atol=1e-13)
+    assert np.max(np.abs(fl["rho"] - rho_o)) <= 1e-14
+
+
+def test_contact_off_is_bitwise_plain(H):
+    """Setting contact and turning it off again gives the plain run bitwise;
+    validation rejects negative or non-finite parameters."""
+    n, bc = (40, 32, 36), (0, 0, 1)
+    parts = _cluster()
+    F0, _, st0, _ = _gpu(H, n, bc, parts, 12, None)
+    sim = H.Simulation(n, bc, 0.8, "fp64", max_particles=len(parts), gravity=(0.0, 0.0, -2e-5))
+    sim.set_particles(parts)
+    sim.set_contact(1.0, 1e-2, 1e-2)
+    sim.set_contact(0.0, 1e-2, 1e-2)
+    sim.step(12)
+    F1, _, st1 = sim.get_forces()
+    for bad in ((-1.0, 1e-3, 0.0), (1.0, -1e-3, 0.0), (float("nan"), 1e-3, 0.0), (1.0, 1e-3, float("inf"))):
+        with pytest.raises(H.HLBMError) as e:
+            sim.set_contact(*bad)
+        assert e.value.code == -1
+    sim.close()
+    assert np.array_equal(F0, F1) and np.array_equal(st0["pos"], st1["pos"])
+
+
+def test_sphere_comes_to_rest_on_wall(H):
+    """A heavy sphere settling onto the bottom wall comes to rest where the
+    wall repulsion carries its submerged weight W: the centre height h
+    satisfies k_w ((2 R + range - 2 h) / range)^2 = W, i.e.
+    h = R + range (1 - sqrt(W / k_w)) / 2.
+
+    The range is chosen so that the sphere's inside cells never reach the
+    wall layer (h >= R + 1/2): there the momentum exchange skips the
+    directions that cross the wall, which pulls the sphere into the wall with
+    about rho / 3 per such cell (measured on the oracle: with range 1 and
+    k_w = 4 W the sphere passes through the wall)."""
+    n, bc, r, g, ratio = (24, 24, 40), (0, 0, 1), 3.0, 2e-4, 3.0
+    rec = W.make_particle(W.SPHERE, (r,), (12.0, 12.0, 9.0), density_ratio=ratio)
+    weight = (ratio - 1.0) * rec["volume"] * g
+    rng, kw = 2.5, 16.0 * weight
+    sim = H.Simulation(n, bc, 0.8, "fp64", max_particles=1, gravity=(0.0, 0.0, -g))
+    sim.set_particles(np.array([rec]))
+    sim.set_contact(rng, 0.0, kw)
+    zs = []
+    for _ in range(40):
+        sim.step(150)
+        _, _, st = sim.get_forces()
+        zs.append(float(st["pos"][0][2]))
+    sim.close()
+    h_eq = r + rng * (1.0 - np.sqrt(weight / kw)) / 2.0
+    _log(f"  heights {np.round(zs[::4], 4)}  equilibrium {h_eq:.4f}  speed {abs(st['vel'][0][2]):.2e}")
+    assert abs(zs[-1] - h_eq) <= 1e-3
+    assert abs(st["vel"][0][2]) <= 1e-5
+    assert min(zs) >= r + 0.5

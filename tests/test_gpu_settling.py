@@ -8,6 +8,11 @@ What is checked:
   * at phi <= 0.1 it lies within [0.9, 1.15] of the Richardson-Zaki power
     law (measured +11 % / +12 % at N = 12; the paper reports agreement with
     the first two correlations at low phi);
+  * at phi = 0.3 the run without contact overestimates the Richardson-Zaki
+    velocity by more than 30 % (the paper's observation at high phi), and the
+    sphere repulsion of hlbm_set_contact (range 2 cells, stiffness 8
+    submerged weights) brings it within [0.95, 1.15] of it (measured +51 % and
+    +4 %), the effect the paper expects of a contact model;
   * resolution: N = 12 and N = 18 agree at phi = 0.1 within 2 % (the paper's
     grid study finds errors below 2 % from N = 12 on) plus twice the
     statistical error of the difference.  A single run is one realisation of
@@ -32,11 +37,11 @@ def S():
     return settling
 
 
-def _run(S, phi, N):
-    key = (phi, N)
+def _run(S, phi, N, contact=None):
+    key = (phi, N, contact)
     if key not in _RUNS:
-        print(f"settling: phi {phi}, N {N}", flush=True)
-        _RUNS[key] = S.run_periodic(phi, N=N, seed=7, gap=1.0)
+        print(f"settling: phi {phi}, N {N}, contact {contact}", flush=True)
+        _RUNS[key] = S.run_periodic(phi, N=N, seed=7, gap=1.0 if phi < 0.25 else 0.2, contact=contact)
         r = _RUNS[key]
         print(f"  u_bar/u* {r['ratio']:.4f} +- {r['ratio_se']:.4f}  RZ {r['rz']:.4f}  GAD {r['gad']:.4f}  BM {r['bm']:.4f}  "
               f"flux {r['mean_flux']:.2e}  {r['seconds']:.1f} s", flush=True)
@@ -52,6 +57,13 @@ def test_settling_velocity_against_correlations(S):
     assert ratios[0] > ratios[1] > ratios[2] > 0.0
     for r in runs[:2]:
         assert 0.9 <= r["ratio"] / r["rz"] <= 1.15
+
+
+def test_contact_closes_the_gap_at_high_phi(S):
+    plain, contact = _run(S, 0.3, 12), _run(S, 0.3, 12, (2.0, 8.0))
+    assert plain["ratio"] / plain["rz"] > 1.3
+    assert 0.95 <= contact["ratio"] / contact["rz"] <= 1.15
+    assert abs(contact["mean_flux"]) <= 0.01 * contact["u_star"]
 
 
 def test_settling_resolution_independence(S):
