@@ -505,6 +505,7 @@ __device__ inline void contact_walls(const Lattice &L, const DevParticle &p, con
 // fixed order (thread t takes slabs t, t + 64, ..., then a fixed wavefront
 // butterfly), the equations of motion, then the particle appended to the tile
 // lists of its new coupling box.
+template <bool CONTACT>
 __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restrict__ parts, int n, int lmax,
                                                 int layers, const double *__restrict__ partial, ContactParams c,
                                                 const double *__restrict__ contact, int *tcnt, int *tlist,
@@ -524,7 +525,7 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
     for (int k = 0; k < 6; ++k) first[k] = src[t * 6 + k];
   // contact: lane b holds chunk b's sum, reduced by the fixed wavefront tree
   double fc[3] = {0.0, 0.0, 0.0};
-  if (c.on && t < contact_chunks(n))
+  if (CONTACT && t < contact_chunks(n))
     for (int a = 0; a < 3; ++a) fc[a] = contact[((size_t)t * n + pid) * 3 + a];
   int lo[3], hi[3];
   cell_box(L, parts[pid].X, parts[pid].rc + 1e-9, lo, hi);
@@ -534,11 +535,11 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
   for (int r = t + 64; r < nrec; r += 64)
     for (int k = 0; k < 6; ++k) acc[k] += src[r * 6 + k];
   for (int k = 0; k < 6; ++k) acc[k] = wave_sum(acc[k]);
-  if (c.on)
+  if (CONTACT)
     for (int a = 0; a < 3; ++a) fc[a] = wave_sum(fc[a]);
   if (t == 0) {
     DevParticle p = parts[pid];
-    if (c.on) {
+    if (CONTACT) {
       contact_walls(L, p, c, fc);
       advance_particle(L, p, acc, fc, status);
     } else {
@@ -622,8 +623,12 @@ hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax,
                           const ContactParams &c, const double *contact, int *tcnt, int *tlist, int *status,
                           hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eom_bin, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, partial, c, contact, tcnt, tlist,
-                     status);
+  if (c.on)
+    hipLaunchKernelGGL(k_eom_bin<true>, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, partial, c, contact, tcnt,
+                       tlist, status);
+  else
+    hipLaunchKernelGGL(k_eom_bin<false>, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, partial, c, contact, tcnt,
+                       tlist, status);
   return hipGetLastError();
 }
 
