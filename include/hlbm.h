@@ -15,7 +15,8 @@
  *   - fluid -> particle: momentum exchange summed over the cells whose centre
  *     is inside the particle, force and torque (Sec. 3.2, MEA, force and
  *     torque equations);
- *   - Newton-Euler equations with gravity and buoyancy (Sec. 2.2, Sec. 5.1);
+ *   - Newton-Euler equations with gravity and buoyancy (Sec. 2.2, Sec. 5.1),
+ *     and optionally a sphere contact force (hlbm_set_contact);
  *   - in the order of the paper's time-step algorithm (Sec. 4.2); its
  *     communication and assignment steps have nothing to do on one GPU.
  *
