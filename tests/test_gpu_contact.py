@@ -133,3 +133,31 @@ def test_sphere_comes_to_rest_on_wall(H):
     assert abs(zs[-1] - h_eq) <= 1e-3
     assert abs(st["vel"][0][2]) <= 1e-5
     assert min(zs) >= r + 0.5
+
+
+def test_many_spheres_contact_chunks_fp64(H, oracle_mod):
+    """1500 small moving spheres on a periodic 64^3 lattice: the pair sums run
+    over 64 partner chunks of 24 (the layout the kernel takes for many
+    particles); 4 steps against the oracle."""
+    n, bc = (64, 64, 64), (0, 0, 0)
+    rng = np.random.default_rng(11)
+    count = 1500
+    pos = rng.uniform(0.0, 64.0, (count, 3))
+    vel = rng.uniform(-2e-3, 2e-3, (count, 3))
+    parts = np.array([W.make_particle(W.SPHERE, (1.0,), tuple(p), vel=tuple(v)) for p, v in zip(pos, vel)])
+    contact = (0.8, 2e-3, 0.0)
+    sim = H.Simulation(n, bc, 0.8, "fp64", max_particles=count, gravity=(0.0, 0.0, -1e-5))
+    sim.set_particles(parts)
+    sim.set_contact(*contact)
+    sim.step(4)
+    F, _, st = sim.get_forces()
+    sim.close()
+    orc = oracle_mod.Oracle(n, bc, 0.8, gravity=(0.0, 0.0, -1e-5), contact=contact)
+    P = orc.to_parts(parts)
+    touching = int(np.count_nonzero(np.abs(orc.contact_forces(P)).sum(1)))
+    Fo, _ = orc.run(P, orc.equilibrium(), 4)
+    _log(f"  {touching} of {count} spheres in contact range; max |dU| {np.abs(st['vel'] - P['U']).max():.3e}")
+    assert touching > 300
+    np.testing.assert_allclose(st["vel"], P["U"], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(st["pos"], P["X"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-10 * np.max(np.abs(Fo)))
