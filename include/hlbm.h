@@ -244,7 +244,7 @@ int hlbm_profile_end(hlbm_ctx *ctx, double *collide_ms, int64_t *launches);
 
 typedef struct hlbm_train_opts {
     int32_t samples;     /* training samples: uniform in the box, or within `band` (band_share) */
-    int32_t holdout;     /* held-out samples within `band` (judge the gate) */
+    int32_t holdout;     /* held-out samples within `band` (evaluate the gate) */
     int32_t iterations;  /* Adam steps */
     int32_t batch;       /* samples per step */
     double lr;           /* initial learning rate */
@@ -255,7 +255,7 @@ typedef struct hlbm_train_opts {
     double band_share;   /* fraction of training samples drawn within `band` (0..1) */
     double gate_rms;     /* accept if held-out RMS error <= gate_rms ... */
     double gate_max;     /* ... and max error <= gate_max (lattice units at ref size) */
-    double ref_circumradius; /* particle size (lattice units) at which the gate is judged */
+    double ref_circumradius; /* particle size (lattice units) at which the gate is evaluated */
     uint64_t seed;       /* sample generator seed */
 } hlbm_train_opts;
 
