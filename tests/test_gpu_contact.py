@@ -29,8 +29,9 @@ def _log(msg):
 
 def _cluster():
     """Spheres in and out of contact range, one near the bottom wall, a pair
-    across the periodic x boundary, and a rounded cube (no contact) touching a
-    sphere; all moving."""
+    across the periodic x boundary, a rounded cube (no contact) touching a
+    sphere, and a sphere driven onto a fixed one (which pushes but does not
+    move); all others moving."""
     recs = [
         W.make_particle(W.SPHERE, (3.0,), (12.3, 14.1, 15.2), vel=(0.004, 0.0, -0.002), omega=(0.0, 0.001, 0.0)),
         W.make_particle(W.SPHERE, (2.5,), (17.6, 15.0, 14.7), vel=(-0.003, 0.001, 0.0)),
@@ -39,6 +40,8 @@ def _cluster():
         W.make_particle(W.SPHERE, (2.0,), (1.2, 24.0, 20.3), vel=(-0.002, 0.0, 0.0)),
         W.make_particle(W.SPHERE, (2.2,), (37.4, 24.6, 20.0), vel=(0.003, 0.0, 0.0)),
         W.make_particle(W.ROUNDED_CUBE, (2.6, 0.5), (12.0, 8.2, 15.5), vel=(0.0, 0.002, 0.0)),
+        W.make_particle(W.SPHERE, (2.0,), (27.5, 22.0, 26.0), fixed=True),
+        W.make_particle(W.SPHERE, (2.0,), (31.6, 22.8, 26.3), vel=(-0.003, 0.0, 0.0)),
     ]
     return np.array(recs)
 
@@ -73,7 +76,8 @@ def test_contact_matches_oracle_fp64(H, oracle_mod):
     plain.run(P2, plain.equilibrium(), 30)
     effect = np.abs(P["U"] - P2["U"]).max()
     _log(f"  contact moved U by {effect:.3e};  max |dU| gpu-oracle {np.abs(st['vel'] - P['U']).max():.3e}")
-    assert np.count_nonzero(np.abs(Fc0).sum(1)) >= 5 and np.all(Fc0[6] == 0.0)
+    assert np.count_nonzero(np.abs(Fc0).sum(1)) >= 7 and np.all(Fc0[6] == 0.0) and np.any(Fc0[8] != 0.0)
+    assert np.array_equal(st["pos"][7], parts["pos"][7]) and np.all(st["vel"][7] == 0.0)
     assert effect > 1e-4
     np.testing.assert_allclose(st["vel"], P["U"], rtol=0, atol=1e-13)
     np.testing.assert_allclose(st["pos"], P["X"], rtol=0, atol=1e-12)
