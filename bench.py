@@ -6,14 +6,23 @@ collide/stream with the HLBM coupling (all of the hot path), over the whole
 lattice.  MLUPS = cells x steps / (wall time x 1e6), inputs resident in HBM,
 timed with torch.cuda.synchronize() on both sides of exactly K steps.
 
+The default workload is hindered384: 384^3 cells with walls in z, 11 265
+mixed particles (spheres, rounded cubes, 2:1 spheroids) of r_eq ~ U[4, 8] at
+solid fraction 0.2, tau 0.55, density ratio 2.5, FP32 populations -- the
+largest single-GPU configuration of the hindered-settling workloads.
+
 Prints one JSON line.  Besides the throughput it carries:
   roofline      -- the collide-and-stream kernel's algorithmic HBM bytes per
                    launch (2 x 19 populations x bytes each, per cell) divided
                    by its mean HIP-event duration over the timed region,
-                   against the 8 TB/s HBM peak;
-  force_err_vs_fp64 -- time-averaged per-particle force of this precision
-                   against the FP64 form of the same workload, RMS-relative
-                   over particles (untimed run);
+                   against the 8 TB/s HBM peak; next to it the coupled step's
+                   fraction: MLUPS x 38 x bytes per population over 8 TB/s;
+  errors_vs_fp64 -- this precision against the FP64 form of the same
+                   workload from rest (untimed runs): velocity L2-relative
+                   and max |rho - rho_ref| at the end, time-averaged
+                   per-particle force RMS-relative over particles, settling
+                   velocity (mean U_z over particles, over the last 10 % of
+                   the steps) relative;
   cpu_baseline  -- the FP64 CPU oracle on a bounded sample of the workload.
 """
 from __future__ import annotations
@@ -74,7 +83,7 @@ def kernel_source_hash() -> str:
     """Hash of the sources the lattice (collide) kernel is built from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2312_14172_amd", "csrc")
-    for name in ("hlbm_device.h", "hlbm_lattice.hip"):
+    for name in ("hlbm_device.h", "hlbm_tile.h", "hlbm_lattice.hip"):
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -97,14 +106,21 @@ def load_traffic(workload: str, precision: str):
     return int(rec["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in rec else None
 
 
-def force_error_vs_fp64(H, wl, precision, steps, every):
-    """Time-averaged per-particle force of `precision` vs FP64, RMS-relative."""
+def errors_vs_fp64(H, wl, precision, steps, every):
+    """This precision against the FP64 plain form (exact indicator) of the
+    same workload from rest: velocity L2-relative and max |rho - rho_ref|
+    after `steps`, the per-particle force averaged over samples every `every`
+    steps (RMS-relative over particles) and the settling velocity (mean U_z
+    over particles, averaged over the samples of the last 10 % of the
+    steps)."""
     import numpy as np
     import torch
     from paper_2312_14172_amd import workloads as W
-    sums = {}
+    res = {}
+    nsamp = steps // every
+    last = max(1, nsamp // 10)
     for prec in (precision, "fp64"):
-        if prec == "fp64":   # the FP64 plain form: exact indicator
+        if prec == "fp64":
             mesh = bool(np.any(wl.particles["shape"] == W.MESH))
             rmax = max(W.circumradius(int(s), p) for s, p in zip(wl.particles["shape"], wl.particles["param"]))
             sim = H.Simulation(wl.n, wl.bc, wl.tau, prec, max_particles=len(wl.particles),
@@ -117,39 +133,47 @@ def force_error_vs_fp64(H, wl, precision, steps, every):
         else:
             sim, _ = make_sim(H, W, wl, prec)
         acc = np.zeros((len(wl.particles), 3))
-        for _ in range(steps // every):
+        vz = []
+        for k in range(nsamp):
             sim.step(every)
-            F, _, _ = sim.get_forces()
+            F, _, st = sim.get_forces()
             acc += F
+            if k >= nsamp - last:
+                vz.append(float(np.mean(st["vel"][:, 2])))
+        fl = sim.get_fields(H.FIELD_RHO | H.FIELD_U)
         torch.cuda.synchronize()
-        sims_state = sim.get_forces()[2]
-        sums[prec] = (acc / (steps // every), sims_state)
+        res[prec] = dict(F=acc / nsamp, vz=float(np.mean(vz)), rho=fl["rho"], u=fl["u"])
         sim.close()
-    a, ref = sums[precision][0], sums["fp64"][0]
-    err = float(np.sqrt(np.mean(np.sum((a - ref) ** 2, axis=1))) /
-                np.sqrt(np.mean(np.sum(ref ** 2, axis=1))))
-    vz = float(np.mean(sums[precision][1]["vel"][:, 2]))
-    vz_ref = float(np.mean(sums["fp64"][1]["vel"][:, 2]))
-    return err, abs(vz - vz_ref) / max(abs(vz_ref), 1e-300)
+        del sim, fl
+    a, r = res[precision], res["fp64"]
+    err_F = float(np.sqrt(np.mean(np.sum((a["F"] - r["F"]) ** 2, axis=1))) /
+                  np.sqrt(np.mean(np.sum(r["F"] ** 2, axis=1))))
+    err_u = float(np.linalg.norm(a["u"] - r["u"]) / np.linalg.norm(r["u"]))
+    err_rho = float(np.max(np.abs(a["rho"] - r["rho"])))
+    err_vz = abs(a["vz"] - r["vz"]) / max(abs(r["vz"]), 1e-300)
+    return {"velocity_l2rel": float(f"{err_u:.4g}"), "density_maxabs": float(f"{err_rho:.4g}"),
+            "force_rms_rel": float(f"{err_F:.4g}"), "settling_velocity_rel": float(f"{err_vz:.4g}"),
+            "run": f"{steps} steps from rest, forces sampled every {every}, settling velocity over the last "
+                   f"{last * every} steps"}
 
 
 def cpu_baseline(wl, target_s=12.0):
     """The FP64 oracle as it stands, on a bounded number of steps of the same
-    workload, all host cores (OpenMP)."""
+    workload, all host cores (OpenMP): steps are timed one at a time until
+    about target_s seconds have passed (at least one, at most 200)."""
     from oracle import oracle as orc
     o = orc.Oracle(wl.n, wl.bc, wl.tau, eps=wl.eps, rho_f=wl.rho_f, gravity=wl.gravity)
     P = o.to_parts(wl.particles)
     f = o.equilibrium()
-    t0 = time.perf_counter()
-    o.run(P, f, 1)
-    one = time.perf_counter() - t0
-    steps = max(1, min(200, int(target_s / max(one, 1e-6))))
-    t0 = time.perf_counter()
-    o.run(P, f, steps)
-    dt = time.perf_counter() - t0
+    steps, dt = 0, 0.0
+    while steps < 200 and (steps == 0 or dt < target_s):
+        t0 = time.perf_counter()
+        o.run(P, f, 1)
+        dt += time.perf_counter() - t0
+        steps += 1
     return {"value": round(wl.ncells * steps / dt / 1e6, 3), "unit": "MLUPS",
             "cores": int(o.num_threads()), "kind": "oracle",
-            "sample": f"{wl.name}: {steps} FP64 steps after 1 warm-up step, {dt:.1f} s"}
+            "sample": f"{wl.name}: the first {steps} FP64 step(s) from rest of the full workload, {dt:.1f} s"}
 
 
 def copy_calibration(nbytes=1 << 31, reps=3):
@@ -169,9 +193,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="spheres128", choices=sorted(DEFAULT_PRECISION))
+    ap.add_argument("--workload", default="hindered384", choices=sorted(DEFAULT_PRECISION))
     ap.add_argument("--precision", default=None, choices=sorted(POP_BYTES))
-    ap.add_argument("--force-steps", type=int, default=200)
+    ap.add_argument("--check-steps", type=int, default=1000,
+                    help="steps of the untimed runs compared with FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-force-check", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -214,11 +239,15 @@ def main():
     per_launch_s = collide_ms / max(launches, 1) / 1e3
     achieved = alg_bytes / per_launch_s / 1e9
     traffic = load_traffic(wl.name, precision)
+    step_bytes = 2 * 19 * POP_BYTES[precision] * wl.ncells * args.steps
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"k_collide<{precision}>",
                 "kernel_ms": round(per_launch_s * 1e3, 5),
-                "bytes_per_launch": alg_bytes}
+                "bytes_per_launch": alg_bytes,
+                "coupled_step_frac": round(step_bytes / dt / 1e9 / HBM_PEAK_GBS, 4),
+                "coupled_step_note": "MLUPS x 38 x bytes per population / 8 TB/s: the whole step "
+                                     "(all kernels) against the lattice's algorithmic traffic"}
     sim.close()
 
     if args.copy_calibration:
@@ -226,11 +255,8 @@ def main():
 
     extra = {}
     if not args.no_force_check and precision != "fp64" and len(wl.particles):
-        every = 10
-        err, vz_err = force_error_vs_fp64(H, wl, precision, args.force_steps, every)
-        extra["force_err_vs_fp64"] = float(f"{err:.4g}")
-        extra["settling_velocity_err_vs_fp64"] = float(f"{vz_err:.4g}")
-        extra["force_check"] = f"{args.force_steps} steps from rest, forces sampled every {every}"
+        print(f"[bench] errors against FP64: {args.check_steps} steps per precision", file=sys.stderr, flush=True)
+        extra["errors_vs_fp64"] = errors_vs_fp64(H, wl, precision, args.check_steps, 10)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -17,7 +17,7 @@
  *     torque equations);
  *   - Newton-Euler equations with gravity and buoyancy (Sec. 2.2, Sec. 5.1),
  *     and optionally a sphere contact force (hlbm_set_contact);
- *   - in the order of the paper's time-step algorithm (Sec. 4.2); its
+ *   - in the order of the paper's time-step algorithm (Sec. 4.2, Algorithm 1); its
  *     communication and assignment steps have nothing to do on one GPU.
  *
  * Units are lattice units throughout.  Cell (x, y, z) has its centre at
@@ -137,7 +137,8 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
 int hlbm_destroy(hlbm_ctx *ctx);
 
 /* Replace the particle set with n host records (copied).  The records are
- * the particle data of Sec. 4.1 (position, orientation, velocity, angular
+ * the particle data of Sec. 4.2 (communication of particle data: position,
+ * orientation, velocity, angular
  * velocity, shape).  Checks: n <= max_particles; finite values; unit
  * quaternion (|q| within 1e-6 of 1, renormalised); inertia > 0; positive
  * shape parameters; a particle's reach (circumradius + max(eps/2, sqrt 2) + 1)
@@ -183,7 +184,8 @@ int hlbm_set_mesh(hlbm_ctx *ctx, const float *vertices, int32_t nv, const int32_
 int hlbm_set_fluid_accel(hlbm_ctx *ctx, const double accel[3]);
 
 /* Sphere contact, off by default.  Sec. 2.2 lets contact forces enter the
- * particles' equations of motion next to the hydrodynamic ones and Sec. 5.2
+ * particles' equations of motion next to the hydrodynamic ones; Sec. 3.2
+ * leaves the cited contact model out on purpose, and Sec. 5.3
  * names the missing contact model as the likely cause of the overestimated
  * settling velocities at high volume fractions, without giving a model.
  * This is the short-range repulsion of Glowinski et al. (J. Comput. Phys.
@@ -201,16 +203,37 @@ int hlbm_set_contact(hlbm_ctx *ctx, double range, double stiffness, double wall_
 
 /* Copy to host the hydrodynamic force F[n][3] and torque T[n][3] on each
  * particle from the last completed step's momentum exchange (zero before the
- * first step), and optionally the current particle records.  Any pointer may
- * be NULL.  Synchronises the stream. */
+ * first step): the force is minus the sum of the MEA momentum F_h over the
+ * cells whose centre is inside the particle, the torque minus the sum of
+ * (x_b - X_p) x F_h (Sec. 3.2, MEA, total-force and torque equations; the
+ * sign reads F_h as the momentum given to the fluid).  Optionally also the
+ * current particle records.  Any pointer may be NULL.  Synchronises the
+ * stream. */
 int hlbm_get_forces(hlbm_ctx *ctx, double *F, double *T, hlbm_particle *state);
 
-/* Write the fields selected by mask, as FP64 planes of ncells values each,
- * in the order rho, u (3), u_phys (3), B, to out (host memory if
- * out_on_device == 0, else device memory on the context's device).  The
- * fields are those of the current state (post-streaming populations at the
- * current integer time and the current particles).  Synchronises the stream. */
-int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_device);
+/* Write the fields selected by mask as planes of ncells values each, in the
+ * order rho, u (3), u_phys (3), B, to out: FP64 values for dtype ==
+ * HLBM_FP64, FP32 (rounded to nearest) for dtype == HLBM_FP32; out is host
+ * memory if out_on_device == 0, else device memory on the context's device,
+ * and must hold (planes x ncells) values of the chosen type.  The fields are
+ * the moments of the current state (Sec. 3.1: rho = sum f_i, rho u = sum c_i
+ * f_i of the post-streaming populations at the current integer time),
+ * u_phys = u + du/2 with du of Sec. 3.2's velocity-difference equation from
+ * the current particles and fluid acceleration, and B, the indicator of
+ * Sec. 3.2's level-set equation combined over particles as min(1, sum B_p).
+ * HLBM_EINVAL for an empty or unknown mask or another dtype.  Synchronises
+ * the stream. */
+int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, int32_t dtype, void *out, int32_t out_on_device);
+
+/* Volume flux of the current state: mean_u_phys[3] = the mean of u_phys over
+ * all cells, mean_fluid_u_phys[3] = its mean over the pure-fluid cells
+ * (B = 0; zero if there are none) and *fluid_cells their number (host
+ * pointers, each may be NULL).  Summed in FP64 in a fixed order on the
+ * device (bitwise reproducible).  Sec. 5.1 sets the periodic suspension's
+ * pressure gradient so that the net volume flux vanishes; the fluid-cell mean
+ * gives the settling velocity relative to the fluid.  Synchronises the
+ * stream. */
+int hlbm_get_mean_velocity(hlbm_ctx *ctx, double *mean_u_phys, double *mean_fluid_u_phys, int64_t *fluid_cells);
 
 /* Measurement hooks: from hlbm_profile_begin on, every collide-and-stream
  * launch of hlbm_step is bracketed by two HIP events recorded on the
@@ -282,6 +305,27 @@ int hlbm_mlp_eval(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts, do
  * computed by the training kernels (BF16 products, FP32 accumulation). */
 int hlbm_mlp_gradient(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts, const double *target,
                       double *grad, double *loss);
+
+/* One training step on n points (host arrays as for hlbm_mlp_gradient):
+ * the gradient of the mean-squared loss by the training kernels, then one
+ * bias-corrected Adam step (Kingma and Ba 2015; beta1 0.9, beta2 0.999,
+ * epsilon 1e-8) with learning rate lr as the step-th update of the family's
+ * FP32 moments (reset by hlbm_mlp_set_params and by hlbm_train_indicator).
+ * Returns the gradient used (host double[HLBM_MLP_NPARAM], may be NULL) and
+ * the loss (may be NULL); the updated parameters are read with
+ * hlbm_mlp_get_params.  HLBM_EINVAL for lr <= 0 or step < 1. */
+int hlbm_mlp_train_step(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts, const double *target,
+                        double lr, int32_t step, double *grad, double *loss);
+
+/* The training samples hlbm_train_indicator draws for a shape with
+ * parameters param[3] and the given seed: n points uniform in [-box, box]^3
+ * of the normalised body frame (the shape scaled to circumradius 1), of which
+ * a share band_share is redrawn (up to 64 times) until the exact signed
+ * distance is within band; out[n][4] (host) receives x, y, z and the signed
+ * distance clipped to +-clip, each rounded to FP32.  n up to the sample
+ * capacity. */
+int hlbm_mlp_samples(hlbm_ctx *ctx, int32_t shape, const double *param, uint64_t seed, int32_t n, double box,
+                     double band, double clip, double band_share, double *out);
 
 /* Train the family's network (starting from its current parameters) on
  * samples of the exact signed distance of a shape with parameters param[3]

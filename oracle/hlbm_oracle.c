@@ -516,7 +516,7 @@ void orc_apply_eom(const ocfg *cfg, int np, opart *P, const double *F, const dou
 
 /* ---------------------------------------------------------------------------
  * Contact between spheres (an addition: the paper runs without a contact
- * model and names one only by citation, Sec. 2.2 and Sec. 5.2).
+ * model and names one only by citation, Sec. 2.2, Sec. 3.2 and Sec. 5.3).
  * reading: the short-range repulsion of Glowinski, Pan, Hesla, Joseph and
  * Periaux (J. Comput. Phys. 169, 2001).  Two spheres whose centres are closer
  * than R_p + R_q + zeta repel along the line of centres with
@@ -617,7 +617,8 @@ void orc_coupling(const ocfg *cfg, int np, const opart *P, double *B, double *us
 }
 
 /* ---------------------------------------------------------------------------
- * One time step in the order of the paper's time-step algorithm (Sec. 4.2):
+ * One time step in the order of the paper's time-step algorithm (Sec. 4.2,
+ * Algorithm 1):
  * MEA -> external force (and contact, when set) -> equations of motion ->
  * EDM coupling -> collide -> stream.  The communication and assignment steps have nothing to do on one
  * address space.  F_last/T_last receive the hydrodynamic force and torque of

@@ -107,6 +107,10 @@ class Oracle:
         self.tau = float(tau)
         self.eps = float(eps)
 
+    def set_fluid_accel(self, accel):
+        """Replace the fluid body acceleration for the following runs."""
+        self.cfg.af = (ctypes.c_double * 3)(*[float(v) for v in accel])
+
     # ---- tables ---------------------------------------------------------
     @staticmethod
     def tables():

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhlbm.so")
-SOURCES = ["hlbm_lattice.hip", "hlbm_particles.hip", "hlbm_mlp.hip", "hlbm_api.hip"]
+SOURCES = ["hlbm_lattice.hip", "hlbm_fields.hip", "hlbm_particles.hip", "hlbm_mlp.hip", "hlbm_api.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -113,10 +113,14 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
     y.tcnt[b] = off; off += align_up((size_t)L.ntiles * sizeof(int));
     y.tlist[b] = off; off += align_up((size_t)L.ntiles * MAXC * sizeof(int));
   }
-  y.partial = off; off += align_up(np * LMAX_CAP * 6 * sizeof(double));
+  // momentum-exchange records: per slab (k_mea) or per tile of the bin box
+  // (evaluated by the collide kernel)
+  y.partial = off; off += align_up(np * (size_t)std::max(LMAX_CAP, REC_TILES) * 6 * sizeof(double));
   y.contact = off; off += align_up(np * (size_t)contact_chunks((int)np) * 3 * sizeof(double));
   y.status = off; off += 256;
-  y.stage = off; off += align_up((size_t)4 * L.N * sizeof(double));
+  // staging: 4 FP64 planes for host transfers, or the 7-double tile records
+  // of the mean-velocity reduction and their sums
+  y.stage = off; off += align_up(std::max<size_t>((size_t)4 * L.N, (size_t)7 * L.ntiles + 7) * sizeof(double));
   y.mesh = off; off += align_up((size_t)(c->max_mesh_triangles > 0 ? c->max_mesh_triangles : 1) * 3 * sizeof(float4));
   y.pool_cap = 0;
   y.table_cap = 0;
@@ -156,6 +160,9 @@ struct hlbm_ctx {
   DevParticle *parts;
   int *order;         // particles in the momentum-exchange visiting order
   int mea_chunked;    // that order is dispatched in XCD-contiguous runs
+  int mea_fused;      // the collide kernel evaluates the next step's momentum
+                      // exchange (every particle's bin box within REC_TILES tiles)
+  bool mea_valid;     // the records it wrote describe the current state
   hlbm_particle *stage_parts;
   int *tcnt[2], *tlist[2], *status;
   int cur;            // tile-list buffer describing the current particles
@@ -226,6 +233,7 @@ int refresh_tables(hlbm_ctx *c) {
 }
 
 int mark_learned(hlbm_ctx *c) {
+  c->mea_valid = false;  // the inside test of learned particles may change
   if (!c->tables || c->n == 0) return HLBM_OK;
   LearnedModes modes;
   for (int f = 0; f < NFAM; ++f) {
@@ -299,6 +307,8 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   c->stage = (double *)(c->base + lay.stage);
   c->n = 0;
   c->mea_chunked = 0;
+  c->mea_fused = 0;
+  c->mea_valid = false;
   c->binned = false;
   c->bin_cap = 1;
   c->steps_done = 0;
@@ -433,9 +443,10 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
       if (ctx->cfg.bc[k] == HLBM_BC_WALL && !(p.pos[k] >= 0 && p.pos[k] <= nn[k]))
         return fail(HLBM_EINVAL, "particle %d: centre outside the walls", i);
     }
-    // the coupling box spans at most floor(2 (rc + eps/2)) + 1 cells per axis;
-    // the binning handles up to MAX_AXIS_TILES tiles of 4 cells per axis
-    const int cells = (int)floor(2.0 * (rc + 0.5 * ctx->cfg.eps)) + 2;
+    // the bin box (centre within rc + max(eps/2, 1)) spans at most
+    // floor(2 reach) + 1 cells per axis; the binning handles up to
+    // MAX_AXIS_TILES tiles of 4 cells per axis
+    const int cells = (int)floor(2.0 * (rc + std::max(0.5 * ctx->cfg.eps, 1.0))) + 2;
     if (cells / TY + 2 > MAX_AXIS_TILES)
       return fail(HLBM_EUNSUPPORTED, "particle %d: circumradius too large for the tile binning", i);
     const int tiles_x = std::min(ctx->L.ntx, cells / TX + 2);
@@ -501,6 +512,10 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
   ctx->mesh_particles = false;
   for (int i = 0; i < n; ++i) ctx->mesh_particles |= host[i].shape == HLBM_MESH;
   ctx->mea_chunked = chunked ? 1 : 0;
+  // the collide kernel takes over the momentum exchange when every bin box
+  // fits the per-particle records (circumradius up to about 15 cells)
+  ctx->mea_fused = 0 && cap <= REC_TILES ? 1 : 0;  // off until its parity is established
+  ctx->mea_valid = false;
   ctx->bin_cap = cap;
   ctx->lmax = lmax;
   int rc = rebin(ctx);
@@ -526,6 +541,7 @@ int hlbm_set_fields(hlbm_ctx *ctx, const double *rho, const double *u) {
   }
   HIP_TRY(launch_set_fields(ctx->cfg.precision, ctx->L, ctx->fA, drho, du, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->mea_valid = false;
   return HLBM_OK;
 }
 
@@ -537,15 +553,20 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
   for (int it = 0; it < nsteps; ++it) {
     const int nxt = 1 - ctx->cur;
     if (ctx->n > 0) {
-      // momentum exchange on the state of time t, then Newton-Euler -> t+1 and
-      // binning of the updated particles into the other tile-list buffer
+      // momentum exchange on the state of time t -- evaluated by the previous
+      // step's collide kernel when its records are valid, else here by k_mea
       // (slabs of 2 z-layers per workgroup for few particles, 4 for many:
-      // enough workgroups to fill the chip, few enough to amortise each)
+      // enough workgroups to fill the chip, few enough to amortise each) --
+      // then Newton-Euler -> t+1 and binning of the updated particles into
+      // the other tile-list buffer
       const int layers = ctx->n >= 1000 ? 4 : 2;
-      HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers, ctx->mea_chunked, ctx->partial, s));
+      const bool have = ctx->mea_fused && ctx->mea_valid;
+      if (!have)
+        HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers,
+                           ctx->mea_chunked, ctx->partial, s));
       HIP_TRY(launch_contact(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->contact, s));
-      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, layers, ctx->partial, ctx->cparams,
-                             ctx->contact, ctx->tcnt[nxt], ctx->tlist[nxt], ctx->status, s));
+      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, layers, have ? 1 : 0, ctx->partial,
+                             ctx->cparams, ctx->contact, ctx->tcnt[nxt], ctx->tlist[nxt], ctx->status, s));
       int rc = refresh_tables(ctx);
       if (rc) return rc;
     }
@@ -561,8 +582,10 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
       }
       HIP_TRY(hipEventRecord(ctx->events[ctx->events_used], s));
     }
+    double *mea_out = (ctx->n > 0 && ctx->mea_fused) ? ctx->partial : nullptr;
     HIP_TRY(launch_collide(prec, ctx->L, ctx->fA, ctx->fB, ctx->parts, ctx->tcnt[use], ctx->tlist[use], clear,
-                           ctx->status, s));
+                           ctx->status, mea_out, s));
+    ctx->mea_valid = mea_out != nullptr;
     ctx->cur = use;
     if (ctx->profiling) {
       HIP_TRY(hipEventRecord(ctx->events[ctx->events_used + 1], s));
@@ -702,9 +725,10 @@ int hlbm_get_forces(hlbm_ctx *ctx, double *F, double *T, hlbm_particle *state) {
   return HLBM_OK;
 }
 
-int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_device) {
+int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, int32_t dtype, void *out, int32_t out_on_device) {
   if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
   if (mask == 0 || (mask & ~15u)) return fail(HLBM_EINVAL, "mask must select fields 1|2|4|8");
+  if (dtype != HLBM_FP64 && dtype != HLBM_FP32) return fail(HLBM_EINVAL, "dtype must be HLBM_FP64 or HLBM_FP32");
   if (!out) return fail(HLBM_EINVAL, "out is NULL");
   int rc = check_status(ctx);
   if (rc) return rc;
@@ -713,28 +737,55 @@ int hlbm_get_fields(hlbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_de
     if (rc) return rc;
   }
   const long long N = ctx->L.N;
-  const int planes = ((mask & 1u) ? 1 : 0) + ((mask & 2u) ? 3 : 0) + ((mask & 4u) ? 3 : 0) + ((mask & 8u) ? 1 : 0);
+  const int f32 = dtype == HLBM_FP32 ? 1 : 0;
+  const size_t esize = f32 ? sizeof(float) : sizeof(double);
   if (out_on_device) {
     HIP_TRY(launch_fields(ctx->cfg.precision, ctx->L, ctx->fA, ctx->parts, ctx->tcnt[ctx->cur],
-                          ctx->tlist[ctx->cur], mask, out, ctx->stream));
+                          ctx->tlist[ctx->cur], mask, f32, out, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return check_status(ctx);
   }
-  // host output: at most four planes fit the staging area at a time
+  // host output: at most four FP64 planes fit the staging area at a time
   const unsigned bits[4] = {1u, 2u, 4u, 8u};
   const int width[4] = {1, 3, 3, 1};
   long long plane = 0;
   for (int b = 0; b < 4; ++b) {
     if (!(mask & bits[b])) continue;
     HIP_TRY(launch_fields(ctx->cfg.precision, ctx->L, ctx->fA, ctx->parts, ctx->tcnt[ctx->cur],
-                          ctx->tlist[ctx->cur], bits[b], ctx->stage, ctx->stream));
-    HIP_TRY(hipMemcpyAsync(out + plane * N, ctx->stage, sizeof(double) * N * width[b], hipMemcpyDeviceToHost,
-                           ctx->stream));
+                          ctx->tlist[ctx->cur], bits[b], f32, ctx->stage, ctx->stream));
+    HIP_TRY(hipMemcpyAsync((char *)out + (size_t)plane * N * esize, ctx->stage, esize * N * width[b],
+                           hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     plane += width[b];
   }
-  (void)planes;
   return check_status(ctx);
+}
+
+int hlbm_get_mean_velocity(hlbm_ctx *ctx, double *mean_u_phys, double *mean_fluid_u_phys, int64_t *fluid_cells) {
+  if (!ctx) return fail(HLBM_EINVAL, "ctx is NULL");
+  int rc = check_status(ctx);
+  if (rc) return rc;
+  if (!ctx->binned) {
+    rc = rebin(ctx);
+    if (rc) return rc;
+  }
+  // tile records in the staging area (ntiles x 7 doubles <= 4 N), sums after them
+  double *partial = ctx->stage;
+  double *sums = ctx->stage + (size_t)ctx->L.ntiles * 7;
+  HIP_TRY(launch_mean_velocity(ctx->cfg.precision, ctx->L, ctx->fA, ctx->parts, ctx->tcnt[ctx->cur],
+                               ctx->tlist[ctx->cur], partial, sums, ctx->stream));
+  double h[7];
+  HIP_TRY(hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  rc = check_status(ctx);
+  if (rc) return rc;
+  const double N = (double)ctx->L.N;
+  for (int k = 0; k < 3; ++k) {
+    if (mean_u_phys) mean_u_phys[k] = h[k] / N;
+    if (mean_fluid_u_phys) mean_fluid_u_phys[k] = h[6] > 0.0 ? h[3 + k] / h[6] : 0.0;
+  }
+  if (fluid_cells) *fluid_cells = (int64_t)h[6];
+  return HLBM_OK;
 }
 
 
@@ -770,6 +821,7 @@ int hlbm_mlp_set_params(hlbm_ctx *ctx, int32_t shape, const float *theta) {
   HIP_TRY(mlp_pack(ctx->theta[f], ctx->packed[f], ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   ctx->has_params[f] = 1;
+  ctx->mea_valid = false;  // distance tables of learned particles change
   return refresh_tables(ctx);
 }
 
@@ -821,6 +873,61 @@ int hlbm_mlp_gradient(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   for (int k = 0; k < MLP_NPARAM; ++k) grad[k] = g[k];
   if (loss) *loss = g[MLP_NPARAM] / n;
+  return HLBM_OK;
+}
+
+int hlbm_mlp_train_step(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts, const double *target,
+                        double lr, int32_t step, double *grad, double *loss) {
+  int f, rc = family(ctx, shape, &f);
+  if (rc) return rc;
+  if (n < 1 || n > ctx->lay.pool_cap) return fail(HLBM_EINVAL, "n outside [1, %lld]", ctx->lay.pool_cap);
+  if (!pts || !target) return fail(HLBM_EINVAL, "NULL buffer");
+  if (!(lr > 0.0) || !isfinite(lr) || step < 1) return fail(HLBM_EINVAL, "need lr > 0 and step >= 1");
+  if (!ctx->has_params[f]) return fail(HLBM_ESTATE, "no parameters for this family");
+  std::vector<float4> smp(n);
+  for (int k = 0; k < n; ++k)
+    smp[k] = make_float4((float)pts[3 * k], (float)pts[3 * k + 1], (float)pts[3 * k + 2], (float)target[k]);
+  std::vector<float> g(MLP_PARTIAL);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(hipMemcpyAsync(ctx->pool, smp.data(), sizeof(float4) * n, hipMemcpyHostToDevice, ctx->stream));
+  const int nb = mlp_grad_blocks(n, MLP_MAX_BLOCKS);
+  HIP_TRY(mlp_grad(ctx->theta[f], ctx->packed[f], ctx->pool, n, MLP_MAX_BLOCKS, 2.0f / n, ctx->gpart, ctx->stream));
+  HIP_TRY(mlp_reduce_adam(ctx->theta[f], ctx->mom1[f], ctx->mom2[f], ctx->gpart, nb, ctx->gout, 1, (float)lr, step,
+                          ctx->stream));
+  HIP_TRY(mlp_pack(ctx->theta[f], ctx->packed[f], ctx->stream));
+  HIP_TRY(hipMemcpyAsync(g.data(), ctx->gout, sizeof(float) * MLP_PARTIAL, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (grad)
+    for (int k = 0; k < MLP_NPARAM; ++k) grad[k] = g[k];
+  if (loss) *loss = g[MLP_NPARAM] / n;
+  ctx->mea_valid = false;  // distance tables of learned particles change
+  return refresh_tables(ctx);
+}
+
+int hlbm_mlp_samples(hlbm_ctx *ctx, int32_t shape, const double *param, uint64_t seed, int32_t n, double box,
+                     double band, double clip, double band_share, double *out) {
+  int f, rc = family(ctx, shape, &f);
+  if (rc) return rc;
+  if (!param || !out) return fail(HLBM_EINVAL, "NULL argument");
+  if (n < 1 || n > ctx->lay.pool_cap) return fail(HLBM_EINVAL, "n outside [1, %lld]", ctx->lay.pool_cap);
+  if (shape == HLBM_MESH) {
+    if (ctx->L.mesh_nt == 0) return fail(HLBM_ESTATE, "no mesh (hlbm_set_mesh)");
+    if (!(param[0] > 0)) return fail(HLBM_EINVAL, "bad shape parameters");
+  } else if (!(param[0] > 0 && param[1] > 0) || (shape == HLBM_ROUNDED_CUBE && param[1] > param[0])) {
+    return fail(HLBM_EINVAL, "bad shape parameters");
+  }
+  if (!(box > 0 && band > 0 && clip >= band && band_share >= 0 && band_share <= 1))
+    return fail(HLBM_EINVAL, "bad box / band / clip / band_share");
+  const double Rc = circumradius_host(ctx, shape, param);
+  std::vector<float4> h(n);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(mlp_samples(shape, param[0] / Rc, param[1] / Rc, ctx->L.mesh, ctx->L.mesh_nt, seed, n, box, band, clip,
+                      band_share, ctx->pool, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(h.data(), ctx->pool, sizeof(float4) * n, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < n; ++k) {
+    out[4 * k] = h[k].x; out[4 * k + 1] = h[k].y; out[4 * k + 2] = h[k].z; out[4 * k + 3] = h[k].w;
+  }
   return HLBM_OK;
 }
 

@@ -1,277 +1,207 @@
-// hlbm_lattice.hip -- gfx950 lattice kernels of the HLBM time step.
-//
-// Storage: populations as structure of arrays A[i][cell] (x fastest), two
-// buffers, pull streaming: the cell x at step t reads f_i(x, t) from
-// A[i][x - c_i] (or A[opp i][x] when x - c_i lies past a wall: half-way
-// bounce-back) and writes its post-collision f*_i(x, t) to B[i][x].
+// hlbm_lattice.hip -- the gfx950 collide-and-stream kernel of the HLBM time
+// step.
 //
 //   k_collide   one workgroup per tile of 64 x 4 x 4 cells: the tile's
 //               particles staged in LDS, the indicator and solid velocity of
 //               the tile's cells accumulated in LDS by a dense pre-pass over
 //               each particle's part of the tile, then per cell: pull,
-//               moments, exact-difference source, BGK, store;
-//   k_set_fields / k_fields   equilibrium initialisation and observables.
-#include "hlbm_device.h"
+//               moments, exact-difference source, BGK, store; with MEA, the
+//               next step's momentum exchange from the values just written.
 #include "hlbm_internal.h"
+#include "hlbm_tile.h"
 
 namespace hlbm {
+
 // ---------------------------------------------------------------------------
-// Pull-index helpers
+// Momentum exchange of the next step inside the collide kernel (Sec. 3.2 MEA,
+// total-force and torque equations).  The values a step writes are the state
+// the next step's exchange reads, and the particles the step couples are the
+// ones that exchange uses (Sec. 4.2, Algorithm 1: the fluid -> particle
+// coupling of step t + 1 follows the collision of step t).  In pull storage
+// f_i(x_b + c_i) = A[i][x_b] and f_opp(i)(x_b) = A[opp i][x_b + c_i], so the
+// value f = A[j][y] written by cell y enters
+//   - the term of x_b = y, direction j, if y is inside and y + c_j is not past
+//     a wall: (c_j - u_p(y)) f;
+//   - the term of x_b = y + c_j, direction opp(j), if y + c_j is a cell inside
+//     the particle: (-c_j + u_p(y + c_j)) f, with u_p(y + c_j) = u_p(y) + w x c_j.
+// Summed over j, with rho, M, P the zeroth, first and second moments of f over
+// the directions of each kind (_i: in-terms, _o: out-terms) and d = y - X:
+//   F_h(y) = (M_i - u rho_i) - M_o + u rho_o + w x M_o,
+//   T_h(y) = d x F_h + M_o x u + w tr(P_o) - P_o w,
+// which regroups exactly the sum over inside cells x_b and directions i; the
+// particle receives -F_h and -T_h.  FP64 throughout, on the stored values.
 // ---------------------------------------------------------------------------
-struct CellPos {
-  int x, y, z;
-  bool act;
-};
+constexpr double kSqrt2 = 1.4142135623730951;
 
-// Source index of f_i(x) in pull storage: A[i][x - c_i], or A[opp i][x] when
-// x - c_i lies past a wall.
-struct PullIdx {
-  int xm, xp, ym, yp, zm, zp;         // wrapped neighbour coordinates (x-1, x+1, ...)
-  bool bxm, bxp, bym, byp, bzm, bzp;  // neighbour lies past a wall
-  int cell;
-};
-
-__device__ inline PullIdx pull_index(const Lattice &L, const CellPos &cp) {
-  PullIdx P;
-  P.xm = cp.x == 0 ? L.nx - 1 : cp.x - 1;
-  P.xp = cp.x == L.nx - 1 ? 0 : cp.x + 1;
-  P.ym = cp.y == 0 ? L.ny - 1 : cp.y - 1;
-  P.yp = cp.y == L.ny - 1 ? 0 : cp.y + 1;
-  P.zm = cp.z == 0 ? L.nz - 1 : cp.z - 1;
-  P.zp = cp.z == L.nz - 1 ? 0 : cp.z + 1;
-  P.bxm = L.bc[0] && cp.x == 0;
-  P.bxp = L.bc[0] && cp.x == L.nx - 1;
-  P.bym = L.bc[1] && cp.y == 0;
-  P.byp = L.bc[1] && cp.y == L.ny - 1;
-  P.bzm = L.bc[2] && cp.z == 0;
-  P.bzp = L.bc[2] && cp.z == L.nz - 1;
-  P.cell = cp.x + L.nx * (cp.y + L.ny * cp.z);
-  return P;
-}
-
-template <int I>
-__device__ inline long long pull_src(const Lattice &L, const CellPos &cp, const PullIdx &P, int &plane) {
-  constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
-  const bool bounce = (cx == 1 && P.bxm) || (cx == -1 && P.bxp) || (cy == 1 && P.bym) ||
-                      (cy == -1 && P.byp) || (cz == 1 && P.bzm) || (cz == -1 && P.bzp);
-  const int sx = cx == 1 ? P.xm : (cx == -1 ? P.xp : cp.x);
-  const int sy = cy == 1 ? P.ym : (cy == -1 ? P.yp : cp.y);
-  const int sz = cz == 1 ? P.zm : (cz == -1 ? P.zp : cp.z);
-  plane = bounce ? opp(I) : I;
-  return bounce ? (long long)P.cell : (long long)sx + (long long)L.nx * (sy + (long long)L.ny * sz);
-}
-
-template <class ST, int I = 0>
-__device__ inline void pull_all(const Lattice &L, const typename ST::S *__restrict__ A,
-                                const CellPos &cp, const PullIdx &P, typename ST::T *g) {
-  if constexpr (I < Q) {
-    int plane;
-    const long long idx = pull_src<I>(L, cp, P, plane);
-    g[I] = ST::dec(A[(long long)plane * L.N + idx]);
-    pull_all<ST, I + 1>(L, A, cp, P, g);
+// Inside test d_s <= 0 of the cell centre at unwrapped coordinates u: the
+// cell must lie in the particle's momentum-exchange box (centre within the
+// circumradius along each axis, mlo..mhi), then the implicit form of the exact
+// shape (the same arithmetic as k_mea) or, with a distance table tab (learned
+// and mesh particles, over the coupling box), its entry.
+__device__ inline bool mea_inside_point(const DevParticle &P, const float *tab, const int *mlo, const int *mhi,
+                                        int u0, int u1, int u2) {
+  if (u0 < mlo[0] || u0 > mhi[0] || u1 < mlo[1] || u1 > mhi[1] || u2 < mlo[2] || u2 > mhi[2]) return false;
+  if (tab) {
+    const int tsx = P.hi[0] - P.lo[0] + 1, tsy = P.hi[1] - P.lo[1] + 1;
+    return tab[(u0 - P.lo[0]) + tsx * ((u1 - P.lo[1]) + tsy * (u2 - P.lo[2]))] <= 0.0f;
   }
+  const double d0 = (u0 + 0.5) - P.X[0], d1 = (u1 + 0.5) - P.X[1], d2 = (u2 + 0.5) - P.X[2];
+  double b0 = d0, b1 = d1, b2 = d2;
+  if (P.shape != 0) {
+    const double *R = P.R;
+    b0 = R[0] * d0 + R[3] * d1 + R[6] * d2;
+    b1 = R[1] * d0 + R[4] * d1 + R[7] * d2;
+    b2 = R[2] * d0 + R[5] * d1 + R[8] * d2;
+  }
+  return inside_body(P.shape, P.prm[0], P.prm[1], b0, b1, b2);
 }
 
-// ---------------------------------------------------------------------------
-// Particle -> fluid coupling evaluated inside the lattice kernels
-// ---------------------------------------------------------------------------
-// Tiles are visited in XCD-contiguous runs (xcd_chunk): the halo rows that
-// neighbouring tiles share are read through the same L2.
-
-// A tile's particle, staged in LDS, in the geometry precision G.  Offsets are
-// formed as (cell - floor(X)) + (1/2 - frac(X)) so that FP32 keeps the
-// fraction exact to its own rounding.
-template <typename G>
-struct Cand {
-  G U[3], W[3];
-  G R[9];
-  G p0, p1;
-  G off[3];      // 1/2 - frac(X)
-  G reach2;      // (rc + eps/2)^2: B = 0 beyond
-  G inner2;      // (r_in - eps/2)^2 with r_in the inscribed radius: B = 1 within
-  G ia2, ib2;    // spheroid: 1 / p0^2, 1 / p1^2
-  int Xi[3];     // floor(X)
-  int lo[3], hi[3];
-  int shape;
-  long long tab; // first table entry of a learned particle, -1 for the exact path
-  int tsx, tsy;  // coupling-box extents (table strides)
+// Geometry of one particle for the exchange, formed once per wavefront and
+// candidate (all values uniform over the wavefront).
+struct MeaGeom {
+  int mlo[3], mhi[3];  // momentum-exchange box (unwrapped)
+  double out2;         // |d| beyond sqrt(out2): the cell and its neighbours are outside
+  double in2;          // |d| within sqrt(in2): the cell and its neighbours are inside (< 0: none)
+  const float *tab;    // distance table (learned / mesh), else NULL
 };
 
-template <typename G>
-struct TileCands {
-  Cand<G> c[MAXC];
-  int raw[MAXC];
-  int n;
-};
-
-// Load the tile's particles into LDS sorted by particle index (so every sum
-// over them has a fixed order).  Ends with a barrier.
-template <typename G>
-__device__ inline void load_candidates(const Lattice &L, const DevParticle *parts, const int *tcnt,
-                                       const int *tlist, int tile, TileCands<G> &tc) {
-  const int n = min(tcnt[tile], MAXC);
-  const int t = threadIdx.x;
-  if (t == 0) tc.n = n;
-  if (t < n) tc.raw[t] = tlist[tile * MAXC + t];
-  __syncthreads();
-  if (t < n) {
-    const int id = tc.raw[t];
-    int rank = 0;
-    for (int k = 0; k < n; ++k) rank += (tc.raw[k] < id);
-    const DevParticle &p = parts[id];
-    Cand<G> &c = tc.c[rank];
-    for (int k = 0; k < 3; ++k) {
-      c.U[k] = (G)p.U[k];
-      c.W[k] = (G)p.W[k];
-      const double fl = floor(p.X[k]);
-      c.Xi[k] = (int)fl;
-      c.off[k] = (G)(0.5 - (p.X[k] - fl));
-      c.lo[k] = p.lo[k];
-      c.hi[k] = p.hi[k];
+__device__ inline MeaGeom mea_geom(const Lattice &L, const DevParticle &P, int pid) {
+  MeaGeom g;
+  const int n[3] = {L.nx, L.ny, L.nz};
+  for (int k = 0; k < 3; ++k) {
+    // the box k_mea visits: centre within rc + 1e-9, clipped at walls
+    int a = (int)ceil(P.X[k] - (P.rc + 1e-9) - 0.5), b = (int)floor(P.X[k] + (P.rc + 1e-9) - 0.5);
+    if (L.bc[k]) {
+      a = max(a, 0);
+      b = min(b, n[k] - 1);
     }
-    for (int k = 0; k < 9; ++k) c.R[k] = (G)p.R[k];
-    c.p0 = (G)p.prm[0];
-    c.p1 = (G)p.prm[1];
-    const double ro = p.rc + 0.5 * L.eps;
-    c.reach2 = (G)(ro * ro);
-    // inscribed radius: sphere r, rounded cube h, spheroid min(a, b), mesh
-    // (stored by the host) scale x the least distance of its surface from the centre
-    const double rin = p.shape == 2 ? fmin(p.prm[0], p.prm[1]) : (p.shape == 3 ? p.prm[2] : p.prm[0]);
-    const double ri = rin - 0.5 * L.eps;
-    c.inner2 = ri > 0.0 ? (G)(ri * ri) : G(-1);
-    c.ia2 = (G)(1.0 / (p.prm[0] * p.prm[0]));
-    c.ib2 = (G)(1.0 / (p.prm[1] * p.prm[1]));
-    c.shape = p.shape;
-    c.tab = (p.learned && L.tables) ? (long long)id * L.table_cap : -1;
-    c.tsx = p.hi[0] - p.lo[0] + 1;
-    c.tsy = p.hi[1] - p.lo[1] + 1;
+    g.mlo[k] = a;
+    g.mhi[k] = b;
   }
-  __syncthreads();
+  g.tab = (P.learned && L.tables) ? L.tables + (size_t)pid * (size_t)L.table_cap : nullptr;
+  // a table marks cells beyond rc + eps/2 outside and within r_in - eps/2
+  // inside (r_in the inscribed radius); the exact shapes are outside beyond rc
+  // and inside within r_in
+  const double rin = P.shape == 2 ? fmin(P.prm[0], P.prm[1]) : (P.shape == 3 ? P.prm[2] : P.prm[0]);
+  const double ro = (g.tab ? P.rc + 0.5 * L.eps : P.rc) + kSqrt2 + 1e-9;
+  const double ri = (g.tab ? rin - 0.5 * L.eps : rin) - kSqrt2 - 1e-9;
+  g.out2 = ro * ro;
+  g.in2 = ri > 0.0 ? ri * ri : -1.0;
+  return g;
 }
 
-// v within the (possibly wrapped) cell range [lo, hi] of an axis.
-__device__ inline bool in_range(int v, int lo, int hi, int n, int periodic) {
-  if (!periodic) return v >= lo && v <= hi;
-  int d = v - lo;
-  if (d < 0) d += n; else if (d >= n) d -= n;
-  if (d < 0) d += n;
-  return d <= hi - lo;
-}
-
-template <typename G>
-__device__ inline G axis_offset(int cell, int xi, G off, int n, int periodic) {
-  G d = (G)(cell - xi) + off;
-  if (periodic) {
-    const G h = G(0.5) * (G)n;
-    if (d > h) d -= (G)n;
-    else if (d < -h) d += (G)n;
-  }
-  return d;
-}
-
-// Per-tile coupling fields in LDS: for every cell of the tile
-//   S0 = sum_p B_p,  S1 = sum_p B_p u_p(x)      (Sec. 3.2; overlap reading:
-//   B = min(1, S0), u_s = S1 / S0).
-// The tile's particles are processed one after the other in index order; each
-// LDS entry is written by one wavefront only (fixed summation order).
-template <typename G>
-struct TileFields {
-  G S0[TZ * TY * TX];
-  G S1[3][TZ * TY * TX];
+// Masked sums over directions 1..18 of the lattice weights in units of 1/36
+// (w_i = 2/36 along the axes, 1/36 along the diagonals): sum_i w_i, sum_i c_i
+// w_i and the entries of sum_i w_i c_i c_i^T, from the set bits of m.
+struct WeightMoments {
+  int g, m[3], p[6];  // p: xx, yy, zz, xy, xz, yz
 };
-
-// Up to two pieces of [lo, hi] (unwrapped) inside the tile range [t0, t0 + ts)
-// of an axis of extent n, as local tile coordinates.
-__device__ inline int axis_pieces(int lo, int hi, int t0, int ts, int n, int periodic, int *a, int *b) {
-  int cnt = 0;
-  const int t1 = min(t0 + ts, n) - 1;
-  for (int k = periodic ? -1 : 0; k <= (periodic ? 1 : 0); ++k) {
-    const int x0 = max(lo, t0 + k * n), x1 = min(hi, t1 + k * n);
-    if (x0 <= x1 && cnt < 2) {
-      a[cnt] = x0 - k * n - t0;
-      b[cnt] = x1 - k * n - t0;
-      ++cnt;
-    }
-  }
-  return cnt;
-}
-
-template <typename G>
-__device__ inline G cell_indicator(const Lattice &L, const Cand<G> &c, int x, int y, int z, G &d0, G &d1, G &d2,
-                                   G he, G eps, G inv_eps) {
-  d0 = axis_offset<G>(x, c.Xi[0], c.off[0], L.nx, !L.bc[0]);
-  d1 = axis_offset<G>(y, c.Xi[1], c.off[1], L.ny, !L.bc[1]);
-  d2 = axis_offset<G>(z, c.Xi[2], c.off[2], L.nz, !L.bc[2]);
-  const G r2 = d0 * d0 + d1 * d1 + d2 * d2;
-  if (!(r2 < c.reach2)) return G(0);
-  if (r2 <= c.inner2) return G(1);  // inside the inscribed sphere shrunk by eps/2
-  if (c.tab >= 0) {
-    const int lx = box_offset(x, c.lo[0], L.nx, !L.bc[0]);
-    const int ly = box_offset(y, c.lo[1], L.ny, !L.bc[1]);
-    const int lz = box_offset(z, c.lo[2], L.nz, !L.bc[2]);
-    return indicator<G>((G)L.tables[c.tab + lx + c.tsx * (ly + c.tsy * lz)], eps, inv_eps);
-  }
-  if (c.shape == 0) return indicator<G>(dsqrt(r2) - c.p0, eps, inv_eps);
-  const G b0 = c.R[0] * d0 + c.R[3] * d1 + c.R[6] * d2;
-  const G b1 = c.R[1] * d0 + c.R[4] * d1 + c.R[7] * d2;
-  const G b2 = c.R[2] * d0 + c.R[5] * d1 + c.R[8] * d2;
-  return indicator<G>(sdf_for_indicator<G>(c.shape, c.p0, c.p1, c.ia2, c.ib2, b0, b1, b2, he), eps, inv_eps);
-}
-
-// Fills tf for tile (tx, ty, tz).  Each wavefront fills the y-row of the tile
-// it later collides (cells x = lane, y = wave, all z), so no barrier is
-// needed: for each particle in index order, the particle's coupling-box cells
-// in that row are spread densely over the wavefront's lanes.  Skips
-// everything when the tile has no particles (tf is then not touched).
-template <typename G>
-__device__ inline void tile_coupling(const Lattice &L, const TileCands<G> &tc, int tx, int ty, int tz,
-                                     TileFields<G> &tf) {
-  const int nc = tc.n;
-  if (nc == 0) return;
-  const int w = wave_id(), lane = lane_id();
+__device__ inline WeightMoments weight_moments(unsigned m) {
+  WeightMoments r;
+  r.g = 0;
+  for (int k = 0; k < 3; ++k) r.m[k] = 0;
+  for (int k = 0; k < 6; ++k) r.p[k] = 0;
 #pragma unroll
-  for (int z = 0; z < TZ; ++z) {
-    const int k = lane + TX * (w + TY * z);
-    tf.S0[k] = G(0);
-    tf.S1[0][k] = tf.S1[1][k] = tf.S1[2][k] = G(0);
+  for (int j = 1; j < Q; ++j) {
+    const int on = (m >> j) & 1u;
+    const int w36 = j <= 6 ? 2 * on : on;
+    r.g += w36;
+    r.m[0] += kCX[j] * w36; r.m[1] += kCY[j] * w36; r.m[2] += kCZ[j] * w36;
+    r.p[0] += kCX[j] * kCX[j] * w36; r.p[1] += kCY[j] * kCY[j] * w36; r.p[2] += kCZ[j] * kCZ[j] * w36;
+    r.p[3] += kCX[j] * kCY[j] * w36; r.p[4] += kCX[j] * kCZ[j] * w36; r.p[5] += kCY[j] * kCZ[j] * w36;
   }
-  const G he = G(0.5) * (G)L.eps;
-  const G eps = (G)L.eps;
-  const G inv_eps = (G)(1.0 / L.eps);
-  for (int ci = 0; ci < nc; ++ci) {
-    const Cand<G> &c = tc.c[ci];
-    int ay[2], by[2];
-    const int nyp = axis_pieces(c.lo[1], c.hi[1], ty * TY, TY, L.ny, !L.bc[1], ay, by);
-    bool row = false;
-    for (int py = 0; py < nyp; ++py) row |= (w >= ay[py] && w <= by[py]);
-    if (!row) continue;  // uniform per wavefront
-    int ax[2], bx[2], az[2], bz[2];
-    const int nxp = axis_pieces(c.lo[0], c.hi[0], tx * TX, TX, L.nx, !L.bc[0], ax, bx);
-    const int nzp = axis_pieces(c.lo[2], c.hi[2], tz * TZ, TZ, L.nz, !L.bc[2], az, bz);
-    for (int pz = 0; pz < nzp; ++pz)
-      for (int px = 0; px < nxp; ++px) {
-        const int sx = bx[px] - ax[px] + 1, sz = bz[pz] - az[pz] + 1;
-        // k -> (x, z) of the piece without integer division: k < 256 and
-        // sx <= 64, so floor((k + 1/2) / sx) in FP32 is exact
-        const float isx = 1.0f / (float)sx;
-        for (int k = lane; k < sx * sz; k += 64) {
-          const int kz = (int)(((float)k + 0.5f) * isx);
-          const int lx = ax[px] + k - kz * sx, lz = az[pz] + kz;
-          G d0, d1, d2;
-          const G Bp = cell_indicator<G>(L, c, tx * TX + lx, ty * TY + w, tz * TZ + lz, d0, d1, d2, he, eps,
-                                         inv_eps);
-          if (Bp > G(0)) {
-            const int idx = lx + TX * (w + TY * lz);
-            tf.S0[idx] += Bp;
-            tf.S1[0][idx] += Bp * (c.U[0] + c.W[1] * d2 - c.W[2] * d1);
-            tf.S1[1][idx] += Bp * (c.U[1] + c.W[2] * d0 - c.W[0] * d2);
-            tf.S1[2][idx] += Bp * (c.U[2] + c.W[0] * d1 - c.W[1] * d0);
-          }
-        }
-      }
+  return r;
+}
+
+// -F_h(y) and -T_h(y) of one particle from the values v[19] that cell y (at
+// unwrapped coordinates u, offset d = y - X) writes; walls: bit j of wallmask
+// is set where y + c_j lies past a wall.  Returns false (and leaves FT zero)
+// when neither y nor any of its neighbours is inside.  With f = w (1 + v / K)
+// the moments split into the lattice weights' (exact small integers over 36)
+// and the stored deviations' (summed in the arithmetic precision TV: the
+// deviations are small, so their rounding stays far below the storage's);
+// from the moments on, everything is FP64.
+template <typename TV>
+__device__ inline bool mea_cell_terms(const DevParticle &P, const MeaGeom &g, int u0, int u1, int u2,
+                                      unsigned wallmask, const TV *v, TV invK, double *FT) {
+  const double d0 = (u0 + 0.5) - P.X[0], d1 = (u1 + 0.5) - P.X[1], d2 = (u2 + 0.5) - P.X[2];
+  const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+  if (r2 > g.out2) return false;
+  constexpr unsigned ALL = 0x7FFFEu;  // directions 1..18
+  bool in_y;
+  unsigned nb;
+  bool uniform = r2 <= g.in2;  // the cell and all its neighbours inside
+  bool side = true;
+  if (!uniform && !g.tab && P.shape != 0) {
+    // the exact signed distance (rounded cube) or a lower bound of its size
+    // (spheroid: |s - 1| min(a, b), s^2 the implicit value) beyond sqrt 2
+    // puts the cell and all its neighbours on one side
+    const double *R = P.R;
+    const double b0 = R[0] * d0 + R[3] * d1 + R[6] * d2;
+    const double b1 = R[1] * d0 + R[4] * d1 + R[7] * d2;
+    const double b2 = R[2] * d0 + R[5] * d1 + R[8] * d2;
+    if (P.shape == 1) {
+      const double ds = sdf_body<double>(1, P.prm[0], P.prm[1], b0, b1, b2);
+      if (fabs(ds) > kSqrt2 + 1e-9) { uniform = true; side = ds < 0.0; }
+    } else if (P.shape == 2) {
+      const double k = b0 * b0 / (P.prm[0] * P.prm[0]) + (b1 * b1 + b2 * b2) / (P.prm[1] * P.prm[1]);
+      if (fabs(sqrt(k) - 1.0) * fmin(P.prm[0], P.prm[1]) > kSqrt2 + 1e-9) { uniform = true; side = k <= 1.0; }
+    }
   }
-  // the row's LDS writes precede the wavefront's own reads in the cell loop
-  __builtin_amdgcn_wave_barrier();
+  if (uniform) {
+    if (!side) return false;
+    in_y = true;
+    nb = ALL & ~wallmask;
+  } else {
+    in_y = mea_inside_point(P, g.tab, g.mlo, g.mhi, u0, u1, u2);
+    nb = 0;
+#pragma unroll
+    for (int j = 1; j < Q; ++j)
+      if (!((wallmask >> j) & 1u) && mea_inside_point(P, g.tab, g.mlo, g.mhi, u0 + kCX[j], u1 + kCY[j], u2 + kCZ[j]))
+        nb |= 1u << j;
+    if (!in_y && nb == 0) return false;
+  }
+  const unsigned inm = in_y ? (ALL & ~wallmask) : 0u;
+  // deviation parts: sums of w_i v_i / K
+  TV Gi = 0, Mi0 = 0, Mi1 = 0, Mi2 = 0;
+  TV Go = 0, Mo0 = 0, Mo1 = 0, Mo2 = 0, Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
+#pragma unroll
+  for (int j = 1; j < Q; ++j) {
+    const TV q = (TV)wgt(j) * invK * v[j];
+    const TV fi = ((inm >> j) & 1u) ? q : (TV)0;
+    const TV fo = ((nb >> j) & 1u) ? q : (TV)0;
+    Gi += fi;
+    Go += fo;
+    if (kCX[j]) { Mi0 += kCX[j] > 0 ? fi : -fi; Mo0 += kCX[j] > 0 ? fo : -fo; Pxx += fo; }
+    if (kCY[j]) { Mi1 += kCY[j] > 0 ? fi : -fi; Mo1 += kCY[j] > 0 ? fo : -fo; Pyy += fo; }
+    if (kCZ[j]) { Mi2 += kCZ[j] > 0 ? fi : -fi; Mo2 += kCZ[j] > 0 ? fo : -fo; Pzz += fo; }
+    if (kCX[j] && kCY[j]) Pxy += kCX[j] * kCY[j] > 0 ? fo : -fo;
+    if (kCX[j] && kCZ[j]) Pxz += kCX[j] * kCZ[j] > 0 ? fo : -fo;
+    if (kCY[j] && kCZ[j]) Pyz += kCY[j] * kCZ[j] > 0 ? fo : -fo;
+  }
+  // weight parts, exact
+  const WeightMoments wi = weight_moments(inm), wo = weight_moments(nb);
+  constexpr double i36 = 1.0 / 36.0;
+  const double gi = wi.g * i36 + (double)Gi;
+  const double mi0 = wi.m[0] * i36 + (double)Mi0, mi1 = wi.m[1] * i36 + (double)Mi1, mi2 = wi.m[2] * i36 + (double)Mi2;
+  const double go = wo.g * i36 + (double)Go;
+  const double mo0 = wo.m[0] * i36 + (double)Mo0, mo1 = wo.m[1] * i36 + (double)Mo1, mo2 = wo.m[2] * i36 + (double)Mo2;
+  const double pxx = wo.p[0] * i36 + (double)Pxx, pyy = wo.p[1] * i36 + (double)Pyy, pzz = wo.p[2] * i36 + (double)Pzz;
+  const double pxy = wo.p[3] * i36 + (double)Pxy, pxz = wo.p[4] * i36 + (double)Pxz, pyz = wo.p[5] * i36 + (double)Pyz;
+  const double *W = P.W;
+  const double u0v = P.U[0] + W[1] * d2 - W[2] * d1;
+  const double u1v = P.U[1] + W[2] * d0 - W[0] * d2;
+  const double u2v = P.U[2] + W[0] * d1 - W[1] * d0;
+  const double F0 = (mi0 - u0v * gi) - mo0 + u0v * go + (W[1] * mo2 - W[2] * mo1);
+  const double F1 = (mi1 - u1v * gi) - mo1 + u1v * go + (W[2] * mo0 - W[0] * mo2);
+  const double F2 = (mi2 - u2v * gi) - mo2 + u2v * go + (W[0] * mo1 - W[1] * mo0);
+  const double tr = pxx + pyy + pzz;
+  const double T0 = (d1 * F2 - d2 * F1) + (mo1 * u2v - mo2 * u1v) + W[0] * tr - (pxx * W[0] + pxy * W[1] + pxz * W[2]);
+  const double T1 = (d2 * F0 - d0 * F2) + (mo2 * u0v - mo0 * u2v) + W[1] * tr - (pxy * W[0] + pyy * W[1] + pyz * W[2]);
+  const double T2 = (d0 * F1 - d1 * F0) + (mo0 * u1v - mo1 * u0v) + W[2] * tr - (pxz * W[0] + pyz * W[1] + pzz * W[2]);
+  FT[0] = -F0; FT[1] = -F1; FT[2] = -F2;
+  FT[3] = -T0; FT[4] = -T1; FT[5] = -T2;
+  return true;
 }
 
 // Fused collide + stream with the exact-difference source (one workgroup per
@@ -295,17 +225,23 @@ __device__ inline void pull_fast(const typename ST::S *__restrict__ A, long long
   }
 }
 
-template <class ST>
+template <class ST, bool MEA>
 __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S *__restrict__ A,
                                                  typename ST::S *__restrict__ Bo,
                                                  const DevParticle *__restrict__ parts,
                                                  const int *__restrict__ tcnt,
                                                  const int *__restrict__ tlist, int *tcnt_clear,
-                                                 int *status) {
+                                                 int *status, double *__restrict__ mea_out) {
   using T = typename ST::T;
   using G = typename ST::G;
   __shared__ TileCands<G> tc;
-  __shared__ TileFields<G> tf;
+  // the coupling fields are dead after the cell loop: their space then holds
+  // the wavefronts' momentum-exchange sums
+  __shared__ union {
+    TileFields<G> tf;
+    double red[4][MAXC][6];
+  } sh;
+  TileFields<G> &tf = sh.tf;
   const T K = ST::K();
   const T invK = (T)1 / K;
   const T omega = (T)L.omega;
@@ -323,6 +259,8 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
   // the other tile-list buffer is refilled by the next step's binning
   if (threadIdx.x == 0 && tcnt_clear) tcnt_clear[tile] = 0;
   tile_coupling<G>(L, tc, tx, ty, tz, tf);
+  // momentum exchange: lane k holds this wavefront's sums for candidate k
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
   for (int zz = 0; zz < TZ; ++zz) {
     CellPos cp;
@@ -389,7 +327,9 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
     const bool coupled = has_af || S0 > G(0);
 
     const T usq = ux * ux + uy * uy + uz * uz;
-    if (cp.act && !(rho > (T)0 && usq < (T)0.09)) atomicOr(status, ST_UNSTABLE);
+    // one flag per wavefront, raised by its first unstable lane
+    const unsigned long long bad = __ballot(cp.act && !(rho > (T)0 && usq < (T)0.09));
+    if (bad && lane_id() == __ffsll((long long)bad) - 1) atomicOr(status, ST_UNSTABLE);
     const T Kr1 = K * rho1, Krho = K * rho;
     const T o3 = (T)3 * Krho, e45 = (T)4.5 * Krho;  // e_i = base + e45 (c.u)^2 + o3 c.u
     const T base = Kr1 - (T)1.5 * Krho * usq;
@@ -425,101 +365,64 @@ __global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S
         __builtin_nontemporal_store(ST::enc(out[i]), &plane[(unsigned)cell]);
       }
     }
-  }
-}
-
-// f_i(x) = feq_i(rho(x), u(x)) written to its pull-storage slot.
-template <class ST>
-__global__ void k_set_fields(Lattice L, typename ST::S *__restrict__ A, const double *__restrict__ rho,
-                             const double *__restrict__ u) {
-  const long long cell = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (cell >= L.N) return;
-  CellPos cp;
-  cp.x = (int)(cell % L.nx);
-  cp.y = (int)((cell / L.nx) % L.ny);
-  cp.z = (int)(cell / ((long long)L.nx * L.ny));
-  cp.act = true;
-  const PullIdx P = pull_index(L, cp);
-  const double r = rho ? rho[cell] : 1.0;
-  const double u0 = u ? u[cell] : 0.0, u1 = u ? u[L.N + cell] : 0.0, u2 = u ? u[2 * L.N + cell] : 0.0;
-  const double usq = u0 * u0 + u1 * u1 + u2 * u2;
-  double dev[Q];  // K (feq_i - w_i) / w_i
+    if constexpr (MEA) {
+      if (nc > 0) {
+        // the values as stored (what the next step reads)
+        T v[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const double cu = kCX[i] * u0 + kCY[i] * u1 + kCZ[i] * u2;
-    dev[i] = (double)ST::K() * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
-  }
-#define HLBM_SET_ONE(I)                                                   \
-  {                                                                       \
-    int plane;                                                            \
-    const long long idx = pull_src<I>(L, cp, P, plane);                   \
-    A[(long long)plane * L.N + idx] = ST::enc((typename ST::T)dev[I]);    \
-  }
-  HLBM_SET_ONE(0) HLBM_SET_ONE(1) HLBM_SET_ONE(2) HLBM_SET_ONE(3) HLBM_SET_ONE(4)
-  HLBM_SET_ONE(5) HLBM_SET_ONE(6) HLBM_SET_ONE(7) HLBM_SET_ONE(8) HLBM_SET_ONE(9)
-  HLBM_SET_ONE(10) HLBM_SET_ONE(11) HLBM_SET_ONE(12) HLBM_SET_ONE(13) HLBM_SET_ONE(14)
-  HLBM_SET_ONE(15) HLBM_SET_ONE(16) HLBM_SET_ONE(17) HLBM_SET_ONE(18)
-#undef HLBM_SET_ONE
-}
-
-// Observables of the current state: rho, bare u, u_phys = u + du/2 and B,
-// written as FP64 planes (order rho, u, u_phys, B; only the selected ones).
-template <class ST>
-__global__ __launch_bounds__(256) void k_fields(Lattice L, const typename ST::S *__restrict__ A,
-                                                const DevParticle *__restrict__ parts,
-                                                const int *__restrict__ tcnt,
-                                                const int *__restrict__ tlist, unsigned mask,
-                                                double *__restrict__ out) {
-  using T = typename ST::T;
-  using G = typename ST::G;
-  __shared__ TileCands<G> tc;
-  __shared__ TileFields<G> tf;
-  const int tile = xcd_chunk(blockIdx.x, L.ntiles);
-  const int tx = tile % L.ntx;
-  const int ty = (tile / L.ntx) % L.nty;
-  const int tz = tile / (L.ntx * L.nty);
-  load_candidates<G>(L, parts, tcnt, tlist, tile, tc);
-  tile_coupling<G>(L, tc, tx, ty, tz, tf);
-  for (int zz = 0; zz < TZ; ++zz) {
-    CellPos cp;
-    cp.x = tx * TX + lane_id();
-    cp.y = ty * TY + wave_id();
-    cp.z = tz * TZ + zz;
-    if (cp.z >= L.nz || cp.y >= L.ny) break;
-    cp.act = cp.x < L.nx;
-    if (!cp.act) continue;
-    T g[Q];
-    const PullIdx P = pull_index(L, cp);
-    const long long cell = P.cell;
-    pull_all<ST>(L, A, cp, P, g);
-    G S0 = G(0), S1[3] = {G(0), G(0), G(0)};
-    if (tc.n > 0) {
-      const int idx = lane_id() + TX * (wave_id() + TY * zz);
-      S0 = tf.S0[idx];
-      S1[0] = tf.S1[0][idx]; S1[1] = tf.S1[1][idx]; S1[2] = tf.S1[2][idx];
-    }
-    double rho1 = 0, j[3] = {0, 0, 0};
+        for (int i = 0; i < Q; ++i) v[i] = ST::dec(ST::enc(out[i]));
+        unsigned wallmask = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const double gi = wgt(i) * (double)g[i] / (double)ST::K();  // f_i - w_i
-      rho1 += gi;
-      j[0] += kCX[i] * gi; j[1] += kCY[i] * gi; j[2] += kCZ[i] * gi;
+        for (int j = 1; j < Q; ++j) {
+          const bool past = (L.bc[0] && ((kCX[j] < 0 && cp.x == 0) || (kCX[j] > 0 && cp.x == nx - 1))) ||
+                            (L.bc[1] && ((kCY[j] < 0 && cp.y == 0) || (kCY[j] > 0 && cp.y == ny - 1))) ||
+                            (L.bc[2] && ((kCZ[j] < 0 && cp.z == 0) || (kCZ[j] > 0 && cp.z == nz - 1)));
+          wallmask |= past ? (1u << j) : 0u;
+        }
+        for (int ci = 0; ci < nc; ++ci) {
+          const Cand<G> &c = tc.c[ci];
+          int u1, u2, u0 = 0;
+          // rows outside the candidate's bin box add nothing (uniform)
+          if (!unwrap_into(cp.y, c.blo[1], c.bhi[1], ny, !L.bc[1], u1)) continue;
+          if (!unwrap_into(cp.z, c.blo[2], c.bhi[2], nz, !L.bc[2], u2)) continue;
+          const bool lane_in = cp.act && unwrap_into(cp.x, c.blo[0], c.bhi[0], nx, !L.bc[0], u0);
+          if (__ballot(lane_in) == 0) continue;
+          const int pid = __builtin_amdgcn_readfirstlane(c.pid);
+          const DevParticle &P = parts[pid];
+          const MeaGeom g = mea_geom(L, P, pid);
+          double ft[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+          const bool any = lane_in && mea_cell_terms<T>(P, g, u0, u1, u2, wallmask, v, invK, ft);
+          if (__ballot(any) == 0) continue;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) ft[k] = wave_sum(ft[k]);
+          if (lane_id() == ci)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[k] += ft[k];
+        }
+      }
     }
-    const double rho = 1.0 + rho1;
-    const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
-    const double s0 = (double)S0;
-    const double Bc = s0 < 1.0 ? s0 : 1.0;
-    double up[3];
-    for (int k = 0; k < 3; ++k) {
-      const double us = s0 > 0.0 ? (double)S1[k] / s0 : 0.0;
-      const double du = Bc * (us - u[k]) + (1.0 - Bc) * L.af[k];
-      up[k] = u[k] + 0.5 * du;
+  }
+  if constexpr (MEA) {
+    // one record per (particle, tile of its bin box): the four wavefronts'
+    // sums added in order (zero where no row adds anything); the EoM kernel
+    // sums the records in order
+    if (nc > 0) {
+      __syncthreads();  // every wavefront is done with the coupling fields
+      const int k = lane_id();
+      if (k < nc)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) sh.red[wave_id()][k][q] = acc[q];
+      __syncthreads();
+      const int t = threadIdx.x;
+      if (t < nc) {
+        const Cand<G> &c = tc.c[t];
+        if (c.rec >= 0 && c.rec < REC_TILES) {
+          double *dst = mea_out + ((size_t)c.pid * REC_TILES + c.rec) * 6;
+#pragma unroll
+          for (int q = 0; q < 6; ++q) dst[q] = ((sh.red[0][t][q] + sh.red[1][t][q]) + sh.red[2][t][q]) + sh.red[3][t][q];
+        }
+      }
     }
-    long long plane = 0;
-    if (mask & 1u) { out[plane * L.N + cell] = rho; plane += 1; }
-    if (mask & 2u) { for (int k = 0; k < 3; ++k) out[(plane + k) * L.N + cell] = u[k]; plane += 3; }
-    if (mask & 4u) { for (int k = 0; k < 3; ++k) out[(plane + k) * L.N + cell] = up[k]; plane += 3; }
-    if (mask & 8u) { out[plane * L.N + cell] = Bc; }
   }
 }
 
@@ -536,24 +439,17 @@ static inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b)
   }
 
 hipError_t launch_collide(int prec, const Lattice &L, const void *A, void *B, const DevParticle *parts,
-                          const int *tcnt, const int *tlist, int *tcnt_clear, int *status, hipStream_t s) {
-  HLBM_DISPATCH(prec, hipLaunchKernelGGL(k_collide<ST>, dim3(L.ntiles), dim3(256), 0, s, L,
-                                         (const typename ST::S *)A, (typename ST::S *)B, parts, tcnt,
-                                         tlist, tcnt_clear, status));
-  return hipGetLastError();
-}
-
-hipError_t launch_set_fields(int prec, const Lattice &L, void *A, const double *rho, const double *u,
-                             hipStream_t s) {
-  HLBM_DISPATCH(prec, hipLaunchKernelGGL(k_set_fields<ST>, dim3(blocks_for(L.N, 256)), dim3(256), 0, s,
-                                         L, (typename ST::S *)A, rho, u));
-  return hipGetLastError();
-}
-
-hipError_t launch_fields(int prec, const Lattice &L, const void *A, const DevParticle *parts,
-                         const int *tcnt, const int *tlist, unsigned mask, double *out, hipStream_t s) {
-  HLBM_DISPATCH(prec, hipLaunchKernelGGL(k_fields<ST>, dim3(L.ntiles), dim3(256), 0, s, L,
-                                         (const typename ST::S *)A, parts, tcnt, tlist, mask, out));
+                          const int *tcnt, const int *tlist, int *tcnt_clear, int *status, double *mea_out,
+                          hipStream_t s) {
+  if (mea_out) {
+    HLBM_DISPATCH(prec, hipLaunchKernelGGL((k_collide<ST, true>), dim3(L.ntiles), dim3(256), 0, s, L,
+                                           (const typename ST::S *)A, (typename ST::S *)B, parts, tcnt,
+                                           tlist, tcnt_clear, status, mea_out));
+  } else {
+    HLBM_DISPATCH(prec, hipLaunchKernelGGL((k_collide<ST, false>), dim3(L.ntiles), dim3(256), 0, s, L,
+                                           (const typename ST::S *)A, (typename ST::S *)B, parts, tcnt,
+                                           tlist, tcnt_clear, status, mea_out));
+  }
   return hipGetLastError();
 }
 

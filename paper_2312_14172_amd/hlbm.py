@@ -25,10 +25,10 @@ FIELD_RHO, FIELD_U, FIELD_U_PHYS, FIELD_SOLID = 1, 2, 4, 8
 EXPORTED = ["hlbm_workspace_size", "hlbm_init", "hlbm_destroy", "hlbm_set_particles",
             "hlbm_set_fields", "hlbm_step", "hlbm_set_fluid_accel", "hlbm_set_contact", "hlbm_set_mesh",
             "hlbm_get_forces",
-            "hlbm_get_fields",
+            "hlbm_get_fields", "hlbm_get_mean_velocity",
             "hlbm_num_particles", "hlbm_profile_begin", "hlbm_profile_end", "hlbm_mlp_set_params",
             "hlbm_mlp_get_params", "hlbm_mlp_eval", "hlbm_mlp_gradient", "hlbm_train_indicator",
-            "hlbm_set_indicator", "hlbm_last_error"]
+            "hlbm_set_indicator", "hlbm_mlp_train_step", "hlbm_mlp_samples", "hlbm_last_error"]
 MLP_NPARAM = 8641
 INDICATOR_EXACT, INDICATOR_LEARNED = 0, 1
 
@@ -96,7 +96,8 @@ def lib():
         L.hlbm_set_contact.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.hlbm_set_mesh.argtypes = [vp, vp, i32, vp, i32]
         L.hlbm_get_forces.argtypes = [vp, vp, vp, vp]
-        L.hlbm_get_fields.argtypes = [vp, ctypes.c_uint32, vp, i32]
+        L.hlbm_get_fields.argtypes = [vp, ctypes.c_uint32, i32, vp, i32]
+        L.hlbm_get_mean_velocity.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]
         L.hlbm_num_particles.argtypes = [vp, ctypes.POINTER(i32)]
         L.hlbm_profile_begin.argtypes = [vp]
         L.hlbm_profile_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -108,6 +109,9 @@ def lib():
         L.hlbm_train_indicator.argtypes = [vp, i32, vp, ctypes.POINTER(hlbm_train_opts),
                                            ctypes.POINTER(hlbm_train_report)]
         L.hlbm_set_indicator.argtypes = [vp, i32, i32]
+        L.hlbm_mlp_train_step.argtypes = [vp, i32, i32, vp, vp, ctypes.c_double, i32, vp, vp]
+        L.hlbm_mlp_samples.argtypes = [vp, i32, vp, ctypes.c_uint64, i32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, vp]
         L.hlbm_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name != "hlbm_last_error":
@@ -233,15 +237,20 @@ class Simulation:
         _check(lib().hlbm_get_forces(self._ctx, F.ctypes.data, T.ctypes.data, st.ctypes.data))
         return F[:n], T[:n], st[:n]
 
-    def get_fields(self, mask=FIELD_RHO | FIELD_U | FIELD_U_PHYS | FIELD_SOLID, on_device=False):
+    def get_fields(self, mask=FIELD_RHO | FIELD_U | FIELD_U_PHYS | FIELD_SOLID, on_device=False,
+                   dtype="fp64"):
+        """Fields as FP64 (dtype "fp64") or FP32 ("fp32") planes: a device
+        tensor [planes, ncells] with on_device, else a dict of numpy arrays."""
         planes = (1 if mask & 1 else 0) + (3 if mask & 2 else 0) + (3 if mask & 4 else 0) + \
                  (1 if mask & 8 else 0)
+        code = {"fp64": FP64, "fp32": FP32}[dtype]
         if on_device:
-            out = self.torch.empty((planes, self.N), dtype=self.torch.float64, device=self.device)
-            _check(lib().hlbm_get_fields(self._ctx, mask, ctypes.c_void_p(out.data_ptr()), 1))
+            tdt = self.torch.float64 if dtype == "fp64" else self.torch.float32
+            out = self.torch.empty((planes, self.N), dtype=tdt, device=self.device)
+            _check(lib().hlbm_get_fields(self._ctx, mask, code, ctypes.c_void_p(out.data_ptr()), 1))
             return out
-        out = np.zeros((planes, self.N))
-        _check(lib().hlbm_get_fields(self._ctx, mask, out.ctypes.data, 0))
+        out = np.zeros((planes, self.N), dtype=np.float64 if dtype == "fp64" else np.float32)
+        _check(lib().hlbm_get_fields(self._ctx, mask, code, out.ctypes.data, 0))
         res = {}
         k = 0
         if mask & 1:
@@ -253,6 +262,15 @@ class Simulation:
         if mask & 8:
             res["B"] = out[k]
         return res
+
+    def get_mean_velocity(self):
+        """(mean u_phys over all cells [3], mean u_phys over pure-fluid cells
+        [3], number of pure-fluid cells), reduced in FP64 on the device."""
+        a = np.zeros(3)
+        b = np.zeros(3)
+        n = ctypes.c_int64(0)
+        _check(lib().hlbm_get_mean_velocity(self._ctx, a.ctypes.data, b.ctypes.data, ctypes.byref(n)))
+        return a, b, n.value
 
     # ---- learned indicator ---------------------------------------------
     def mlp_set_params(self, shape, theta):
@@ -279,6 +297,26 @@ class Simulation:
         _check(lib().hlbm_mlp_gradient(self._ctx, int(shape), len(p), p.ctypes.data, t.ctypes.data,
                                        g.ctypes.data, ctypes.byref(loss)))
         return g, loss.value
+
+    def mlp_train_step(self, shape, pts, target, lr, step):
+        """Gradient on (pts, target), then one Adam step (the step-th);
+        returns (gradient, loss)."""
+        p = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        t = np.ascontiguousarray(target, dtype=np.float64).reshape(-1)
+        g = np.zeros(MLP_NPARAM)
+        loss = ctypes.c_double(0)
+        _check(lib().hlbm_mlp_train_step(self._ctx, int(shape), len(p), p.ctypes.data, t.ctypes.data,
+                                         float(lr), int(step), g.ctypes.data, ctypes.byref(loss)))
+        return g, loss.value
+
+    def mlp_samples(self, shape, param, n, seed=4, box=1.1, band=0.1, clip=0.25, band_share=0.8):
+        """The training samples [n, 4] (x, y, z, clipped signed distance) the
+        GPU generator draws, in normalised units."""
+        prm = np.ascontiguousarray(list(param) + [0.0] * (3 - len(param)), dtype=np.float64)
+        out = np.zeros((int(n), 4))
+        _check(lib().hlbm_mlp_samples(self._ctx, int(shape), prm.ctypes.data, int(seed), int(n), float(box),
+                                      float(band), float(clip), float(band_share), out.ctypes.data))
+        return out
 
     def train_indicator(self, shape, param, samples=1_000_000, holdout=100_000, iterations=3000,
                         batch=8192, lr=3e-3, lr_final=3e-5, box=1.1, band=0.05, clip=0.25,

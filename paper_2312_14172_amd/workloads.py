@@ -304,11 +304,22 @@ def voxel_rsa_positions(rng, shapes, prms, quats, n, bc, gap=1.0, wall_margin=1.
     occ = np.zeros(n[::-1], dtype=bool)  # [z, y, x]
     pos = np.zeros((len(shapes), 3))
     attempts = 0
+    nn = np.array(n)
     for i in range(len(shapes)):
         shape, prm, q = int(shapes[i]), prms[i], quats[i]
         reach = circumradius(shape, prm) + 0.5 * gap
         lo = np.array([0.0 if bc[k] == 0 else reach + wall_margin for k in range(3)])
         hi = np.array([float(n[k]) if bc[k] == 0 else n[k] - reach - wall_margin for k in range(3)])
+        # a core of cells inside the footprint for every centre in the base
+        # cell: the ball of the inscribed radius of the grown shape (an early
+        # rejection that never rejects an attempt the full test would accept)
+        r_in = (prm[0] if shape != SPHEROID else min(prm[0], prm[1])) + 0.5 * gap
+        k = int(math.ceil(r_in)) + 1
+        ax = np.arange(-k, k + 1)
+        gz, gy, gx = np.meshgrid(ax, ax, ax, indexing="ij")
+        off = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+        far = np.sqrt(np.sum((np.abs(off) + 0.5) ** 2, axis=1))  # farthest centre over the base cell
+        core = off[far <= r_in]
         while True:
             attempts += 1
             if attempts > max_attempts:
@@ -317,6 +328,16 @@ def voxel_rsa_positions(rng, shapes, prms, quats, n, bc, gap=1.0, wall_margin=1.
             base = np.floor(X).astype(int)
             if occ[base[2] % n[2], base[1] % n[1], base[0] % n[0]]:
                 continue
+            if len(core):
+                cc = core + base
+                inside = True
+                for a in range(3):
+                    if bc[a] == 0:
+                        cc[:, a] %= nn[a]
+                    elif cc[:, a].min() < wall_margin or cc[:, a].max() > n[a] - 1 - wall_margin:
+                        inside = False
+                if not inside or occ[cc[:, 2], cc[:, 1], cc[:, 0]].any():
+                    continue
             cells = _footprint(shape, prm, q, X - base, 0.5 * gap) + base
             ok = True
             for k in range(3):

@@ -8,7 +8,8 @@ steps.  The velocity error is taken relative to max(|u_ref|, 1e-4) per cell
 moves u by ~1e-17, i.e. 1e-11 relative at the |u| ~ 3e-6 of the settling
 sphere, so a purely relative bar would measure the oracle's own round-off;
 FP32 (shifted storage f - w) -- L2-relative velocity <= 1e-5, force <= 1e-4;
-FP16S -- stated error bounds measured against FP64."""
+FP16S -- velocity and force <= 5e-3 (measured ~1e-4 and ~3e-5 on the
+single sphere)."""
 import numpy as np
 import pytest
 
@@ -83,7 +84,7 @@ def test_single_sphere_fp64_matches_oracle(H, oracle_mod):
                                atol=1e-10 * np.max(np.abs(r["P"]["U"][0])))
 
 
-@pytest.mark.parametrize("precision,tol_u,tol_F", [("fp32", 1e-5, 1e-4), ("fp16s", 2e-2, 2e-2)])
+@pytest.mark.parametrize("precision,tol_u,tol_F", [("fp32", 1e-5, 1e-4), ("fp16s", 5e-3, 5e-3)])
 def test_single_sphere_reduced_precision(H, oracle_mod, precision, tol_u, tol_F):
     wl = W.single_sphere()
     _log(f"gpu: sphere32 {precision} 100 steps")
@@ -232,3 +233,48 @@ def test_fluid_accel_changed_between_steps(H):
     err_rho = float(np.max(np.abs(fl["rho"] - 1.0)))
     _log(f"  max|u - n a| {err_u:.2e}  max|rho - 1| {err_rho:.2e}")
     assert err_u <= 1e-15 and err_rho <= 1e-14
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", None), ("fp32", 1e-5)])
+def test_fluid_accel_with_moving_particles(H, oracle_mod, precision, tol):
+    """A fluid body acceleration acts outside the solid through
+    du = B (u_s - u) + (1 - B) a_f (Sec. 3.2 velocity difference; Sec. 5.1
+    drives the periodic suspension with such a pressure gradient) on moving,
+    spinning particles of all three shapes, and is changed between two runs
+    of steps on both sides; fields (including u_phys with a_f) and forces
+    against the oracle."""
+    n, bc = (70, 26, 30), (0, 0, 1)
+    parts = W.random_particles_small(n, 4, 21, r_eq=(2.5, 3.5), bc=bc)
+    a1, a2 = (2e-6, -1e-6, 3e-6), (-1.5e-6, 2.5e-6, -4e-6)
+    rho, u = W.smooth_fields(n, 31, rho_amp=1e-3, u_amp=1e-2)
+    _log(f"gpu: fluid accel with particles {precision}")
+    sim = H.Simulation(n, bc, 0.8, precision, max_particles=len(parts), gravity=(0, 0, -1e-5), fluid_accel=a1)
+    sim.set_fields(rho, u)
+    sim.set_particles(parts)
+    sim.step(12)
+    sim.set_fluid_accel(a2)
+    sim.step(13)
+    F, T, st = sim.get_forces()
+    fl = sim.get_fields()
+    sim.close()
+    orc = oracle_mod.Oracle(n, bc, 0.8, gravity=(0, 0, -1e-5), fluid_accel=a1)
+    P = orc.to_parts(parts)
+    f = orc.equilibrium(rho, u)
+    orc.run(P, f, 12)
+    orc.set_fluid_accel(a2)
+    Fo, To = orc.run(P, f, 13)
+    rho_o, u_o, up_o, B_o = orc.fields(P, f)
+    e_u = _l2rel(fl["u"], u_o, U_FLOOR)
+    e_up = _l2rel(fl["u_phys"], up_o, U_FLOOR)
+    e_F = float(np.max(np.abs(F - Fo)) / np.max(np.abs(Fo)))
+    _log(f"  L2rel(u)={e_u:.3e} L2rel(u_phys)={e_up:.3e} relF={e_F:.3e}")
+    if precision == "fp64":
+        assert e_u <= 1e-12 and e_up <= 1e-12
+        assert np.max(np.abs(fl["rho"] - rho_o)) <= 1e-14
+        np.testing.assert_allclose(fl["B"], B_o, rtol=0, atol=1e-13)
+        assert e_F <= 1e-10
+        np.testing.assert_allclose(T, To, rtol=0, atol=1e-9 * np.max(np.abs(To)))
+        np.testing.assert_allclose(st["pos"], P["X"], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(st["omega"], P["W"], rtol=0, atol=1e-13)
+    else:
+        assert e_u <= tol and e_up <= tol and e_F <= 1e-4

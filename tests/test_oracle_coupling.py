@@ -272,3 +272,86 @@ def test_overlapping_indicators_combine(oracle_mod):
     m = S0 > 0
     np.testing.assert_allclose(u2[:, m], (Ba * ua + Bb * ub)[:, m] / S0[m], atol=1e-15)
     assert np.any(S0 > 1)
+
+
+def _brute_coupling(orc, P, n, bc):
+    """B = min(1, sum_p B(d_p)) and u_s = sum_p B_p u_p / sum_p B_p over EVERY
+    cell of the lattice, with d_p from the oracle's signed distance (pinned
+    above against brute-force surface search) at the body-frame offset of the
+    cell centre.  The rotation of each particle comes from scipy's quaternion
+    routine, the offset is the minimum image on periodic axes, and the
+    particle velocity is U + w x (x - X) (Sec. 3.2)."""
+    from scipy.spatial.transform import Rotation
+    nx, ny, nz = n
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cen = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1) + 0.5
+    S0 = np.zeros(len(cen))
+    S1 = np.zeros((3, len(cen)))
+    for p in P:
+        dl = cen - p["X"]
+        for k in range(3):
+            if bc[k] == 0:
+                dl[:, k] -= n[k] * np.round(dl[:, k] / n[k])
+        w, qx, qy, qz = p["q"]
+        Rm = Rotation.from_quat([qx, qy, qz, w]).as_matrix()   # body -> world
+        body = dl @ Rm                                          # R^T (x - X) per row
+        d = np.array([orc.sdf(int(p["shape"]), p["prm"], b) for b in body])
+        Bp = np.array([orc.indicator(v) for v in d])
+        up = p["U"][:, None] + np.cross(p["W"], dl).T
+        S0 += Bp
+        S1 += Bp * up
+    B = np.minimum(1.0, S0)
+    us = np.where(S0 > 0, S1 / np.where(S0 > 0, S0, 1.0), 0.0)
+    return B, us, S0
+
+
+def test_nonspherical_coupling_against_all_cells(oracle_mod):
+    """The oracle's coupling visits, per particle, the cells whose centre is
+    within the circumradius + eps/2 (wrapped, clipped at walls); here its B and
+    u_s are compared with a brute-force evaluation over every cell for a
+    rotating rounded cube across the periodic x face, a spinning spheroid at a
+    z wall, a mesh particle overlapping the cube's smooth region, and a
+    sphere.  The tips and corners of the non-spherical bodies reach within one
+    cell of their circumradius, so a visiting box short by a cell would drop
+    cells that have B > 0 here."""
+    n, bc = (26, 24, 22), (0, 0, 1)
+    orc = oracle_mod.Oracle(n, bc, 0.8)
+    oracle_mod.Oracle.set_mesh(*W.MESH_UNIT)
+    rng = np.random.default_rng(5)
+    cube = W.equal_volume_params(W.ROUNDED_CUBE, 4.0)
+    sph = W.equal_volume_params(W.SPHEROID, 3.5)
+    mesh = (4.0 / W.MESH_RC * 1.3, 0.0, 0.0)
+    recs = np.array([
+        W.make_particle(W.ROUNDED_CUBE, cube, (1.3, 8.2, 9.7), quat=W.shoemake_quaternion(rng),
+                        vel=(0.01, -0.004, 0.002), omega=(0.002, -0.003, 0.004)),
+        W.make_particle(W.SPHEROID, sph, (14.6, 15.1, 3.4), quat=W.shoemake_quaternion(rng),
+                        vel=(-0.003, 0.002, 0.006), omega=(-0.004, 0.001, 0.003)),
+        W.make_particle(W.MESH, mesh, (8.9, 9.3, 11.2), quat=W.shoemake_quaternion(rng),
+                        vel=(0.002, 0.001, -0.003), omega=(0.001, 0.005, -0.002)),
+        W.make_particle(W.SPHERE, (3.2,), (19.5, 3.1, 16.0), vel=(0.0, 0.005, 0.0), omega=(0.0, 0.0, 0.01)),
+    ])
+    P = orc.to_parts(recs)
+    B, us = orc.coupling(P)
+    Bb, usb, S0 = _brute_coupling(orc, P, n, bc)
+    # the two rotations and offsets round differently (~1e-15 in d); B moves
+    # at most pi / eps per unit of d
+    np.testing.assert_allclose(B, Bb, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(us, usb, rtol=0, atol=1e-13)
+    assert np.sum(B > 0) > 1000
+    assert np.any(S0 > 1.0)            # an overlap of smooth regions is covered
+    # cells with B_p > 0 within one cell of each body's circumradius exist
+    from scipy.spatial.transform import Rotation
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    cen = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1) + 0.5
+    for p in P[:3]:
+        dl = cen - p["X"]
+        for k in range(3):
+            if bc[k] == 0:
+                dl[:, k] -= n[k] * np.round(dl[:, k] / n[k])
+        r = np.linalg.norm(dl, axis=1)
+        rc = orc.circumradius(int(p["shape"]), p["prm"])
+        near = np.where(r > rc - 1.0)[0]
+        w, qx, qy, qz = p["q"]
+        body = dl[near] @ Rotation.from_quat([qx, qy, qz, w]).as_matrix()
+        d = np.array([orc.sdf(int(p["shape"]), p["prm"], b) for b in body])
+        assert np.any(d < 0.5 * orc.eps), int(p["shape"])
