@@ -68,6 +68,19 @@ extern "C" {
 #define HLBM_FP32 1  /* FP32 arithmetic, FP32 storage, K = 1 */
 #define HLBM_FP16S 2 /* FP32 arithmetic, FP16 storage, K = 256 */
 
+/* particle -> fluid coupling of the collision (hlbm_config.coupling) */
+#define HLBM_COUPLING_HLBM 0 /* BGK with the exact-difference source (Sec. 3.2) */
+#define HLBM_COUPLING_PSM 1  /* partially saturated collision of Noble and Torczynski
+                                (1998), the method family Sec. 3.2 names as a host of
+                                the scheme: where B > 0,
+                                f*_i = f_i - (1 - B_n)(f_i - feq_i(rho, u))/tau
+                                       + B_n (f_opp(i) - feq_opp(i)(rho, u)
+                                              + feq_i(rho, u_s) - f_i)
+                                       + (1 - B_n)(feq_i(rho, u + a_f) - feq_i(rho, u)),
+                                B_n = B (tau - 1/2) / ((1 - B) + (tau - 1/2)); the
+                                particle force stays the momentum exchange's
+                                (Sec. 4.2, Algorithm 1) */
+
 /* particle shapes (body-frame parameters in hlbm_particle.param) */
 #define HLBM_SPHERE 0       /* param[0] = radius */
 #define HLBM_ROUNDED_CUBE 1 /* param[0] = half-extent h, param[1] = corner radius
@@ -84,7 +97,8 @@ extern "C" {
 /* field selection for hlbm_get_fields */
 #define HLBM_FIELD_RHO 1u    /* rho = sum_i f_i                              (1 plane) */
 #define HLBM_FIELD_U 2u      /* bare u = sum_i c_i f_i / rho                 (3 planes) */
-#define HLBM_FIELD_U_PHYS 4u /* u + du/2 with du from the current particles  (3 planes) */
+#define HLBM_FIELD_U_PHYS 4u /* u + du/2 with du from the current particles  (3 planes);
+                                with HLBM_COUPLING_PSM du = B_n (u_s - u) + (1 - B_n) a_f */
 #define HLBM_FIELD_SOLID 8u  /* B = min(1, sum_p B_p)                        (1 plane) */
 
 typedef struct hlbm_config {
@@ -104,6 +118,7 @@ typedef struct hlbm_config {
     double learned_max_circumradius; /* largest circumradius of a particle that
                              may use a learned indicator (sizes the tables) */
     int32_t max_mesh_triangles; /* capacity of the HLBM_MESH shape's mesh, >= 0 */
+    int32_t coupling;     /* HLBM_COUPLING_HLBM (0) or HLBM_COUPLING_PSM */
 } hlbm_config;
 
 typedef struct hlbm_particle {

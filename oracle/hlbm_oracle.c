@@ -69,6 +69,7 @@ typedef struct {
     double rho_f;    /* fluid density used in the buoyancy term */
     double g[3];     /* gravity vector */
     double af[3];    /* fluid body acceleration (Poiseuille / sphere-array drag) */
+    int coupling;    /* 0: HLBM (EDM source), 1: partially saturated method */
 } ocfg;
 
 enum { SH_SPHERE = 0, SH_ROUNDED_CUBE = 1, SH_SPHEROID = 2, SH_MESH = 3 };
@@ -381,12 +382,56 @@ void orc_collide_cell(const ocfg *cfg, const double *f, double B, const double *
     }
 }
 
+/* Weight of the solid collision in the partially saturated method (Noble and
+ * Torczynski 1998, whose family of methods Sec. 3.2 names as a possible host
+ * of the decomposition): B_n = B (tau - 1/2) / ((1 - B) + (tau - 1/2)), with
+ * the solid fraction B of the cell. */
+double orc_psm_weight(double B, double tau) {
+    return B * (tau - 0.5) / ((1.0 - B) + (tau - 0.5));
+}
+
+/* Partially saturated collision at one cell:
+ *   rho, u from f;  B_n = orc_psm_weight(B, tau);
+ *   Omega^s_i = f_opp(i) - feq_opp(i)(rho, u) + feq_i(rho, u_s) - f_i
+ *   f*_i = f_i - (1 - B_n)(f_i - feq_i(rho, u))/tau + B_n Omega^s_i
+ *          + (1 - B_n) (feq_i(rho, u + a_f) - feq_i(rho, u)).
+ * reading: the solid fraction and solid velocity are those of the HLBM
+ * coupling (B = min(1, sum B_p), u_s the B-weighted particle velocity); a
+ * fluid body acceleration a_f acts on the fluid part through the
+ * exact-difference source. */
+void orc_collide_cell_psm(const ocfg *cfg, const double *f, double B, const double *us, double *fs) {
+    init_tables();
+    double rho = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+        rho += f[i];
+        for (int k = 0; k < 3; ++k) j[k] += C[i][k] * f[i];
+    }
+    double u[3], ua[3];
+    for (int k = 0; k < 3; ++k) {
+        u[k] = j[k] / rho;
+        ua[k] = u[k] + cfg->af[k];
+    }
+    double feq[Q], feqs[Q], feqa[Q];
+    orc_feq(rho, u, feq);
+    orc_feq(rho, us, feqs);
+    orc_feq(rho, ua, feqa);
+    const double Bn = orc_psm_weight(B, cfg->tau);
+    for (int i = 0; i < Q; ++i) {
+        const int o = OPP[i];
+        const double omega_s = f[o] - feq[o] + feqs[i] - f[i];
+        fs[i] = f[i] - (1.0 - Bn) * (f[i] - feq[i]) / cfg->tau + Bn * omega_s + (1.0 - Bn) * (feqa[i] - feq[i]);
+    }
+}
+
 void orc_collide(const ocfg *cfg, const double *f, const double *B, const double *us, double *fs) {
     long N = orc_ncells(cfg);
 #pragma omp parallel for schedule(static) if (N >= 4096)
     for (long x = 0; x < N; ++x) {
         double uu[3] = {us[x], us[N + x], us[2 * N + x]};
-        orc_collide_cell(cfg, f + Q * x, B[x], uu, fs + Q * x);
+        if (cfg->coupling == 1)
+            orc_collide_cell_psm(cfg, f + Q * x, B[x], uu, fs + Q * x);
+        else
+            orc_collide_cell(cfg, f + Q * x, B[x], uu, fs + Q * x);
     }
 }
 
@@ -655,8 +700,10 @@ int orc_run(const ocfg *cfg, int np, opart *P, double *f, int nsteps, double *Fl
     return 0;
 }
 
-/* Reported fields: bare rho and u, the EDM physical velocity
- * u_phys = u + du/2 with du from the current particles, and B. */
+/* Reported fields: bare rho and u, the physical velocity u_phys = u + du/2
+ * with du from the current particles (EDM: du = B (u_s - u) + (1 - B) a_f;
+ * partially saturated method: the velocity change of its collision per unit
+ * density, du = B_n (u_s - u) + (1 - B_n) a_f), and B. */
 void orc_fields(const ocfg *cfg, int np, const opart *P, const double *f, double *rho, double *u,
                 double *uphys, double *B) {
     long N = orc_ncells(cfg);
@@ -665,8 +712,9 @@ void orc_fields(const ocfg *cfg, int np, const opart *P, const double *f, double
     orc_moments(cfg, f, rho, u);
     orc_coupling(cfg, np, P, Bt, us);
     for (long x = 0; x < N; ++x) {
+        const double Bw = cfg->coupling == 1 ? orc_psm_weight(Bt[x], cfg->tau) : Bt[x];
         for (int k = 0; k < 3; ++k) {
-            double du = Bt[x] * (us[k * N + x] - u[k * N + x]) + (1.0 - Bt[x]) * cfg->af[k];
+            double du = Bw * (us[k * N + x] - u[k * N + x]) + (1.0 - Bw) * cfg->af[k];
             uphys[k * N + x] = u[k * N + x] + 0.5 * du;
         }
         if (B) B[x] = Bt[x];

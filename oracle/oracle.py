@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
 class OCfg(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 3), ("bc", ctypes.c_int * 3), ("tau", ctypes.c_double),
                 ("eps", ctypes.c_double), ("rho_f", ctypes.c_double),
-                ("g", ctypes.c_double * 3), ("af", ctypes.c_double * 3)]
+                ("g", ctypes.c_double * 3), ("af", ctypes.c_double * 3), ("coupling", ctypes.c_int)]
 
 
 # the oracle's own particle record
@@ -72,6 +72,9 @@ def lib():
         L.orc_equilibrium_field.argtypes = [cp, vp, vp, dp]
         L.orc_moments.argtypes = [cp, dp, dp, dp]
         L.orc_collide_cell.argtypes = [cp, dp, ctypes.c_double, dp, dp]
+        L.orc_collide_cell_psm.argtypes = [cp, dp, ctypes.c_double, dp, dp]
+        L.orc_psm_weight.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_psm_weight.restype = ctypes.c_double
         L.orc_collide.argtypes = [cp, dp, dp, dp, dp]
         L.orc_stream.argtypes = [cp, dp, dp]
         L.orc_mea.argtypes = [cp, ctypes.c_int, vp, dp, dp, dp]
@@ -94,7 +97,9 @@ class Oracle:
     """A lattice configuration plus the oracle's passes over numpy arrays."""
 
     def __init__(self, n, bc=(0, 0, 0), tau=0.8, eps=0.5, rho_f=1.0, gravity=(0.0, 0.0, 0.0),
-                 fluid_accel=(0.0, 0.0, 0.0), contact=None):
+                 fluid_accel=(0.0, 0.0, 0.0), contact=None, coupling="hlbm"):
+        # coupling: "hlbm" (exact-difference source) or "psm" (partially
+        # saturated collision); the particle force is the MEA's in both
         # contact: None, or (range zeta, stiffness k, wall stiffness k_w) of the
         # sphere repulsion added to the equations of motion
         self.contact = tuple(float(v) for v in contact) if contact else (0.0, 0.0, 0.0)
@@ -102,7 +107,7 @@ class Oracle:
         self.bc = tuple(int(v) for v in bc)
         self.cfg = OCfg((ctypes.c_int * 3)(*self.n), (ctypes.c_int * 3)(*self.bc), float(tau),
                         float(eps), float(rho_f), (ctypes.c_double * 3)(*gravity),
-                        (ctypes.c_double * 3)(*fluid_accel))
+                        (ctypes.c_double * 3)(*fluid_accel), {"hlbm": 0, "psm": 1}[coupling])
         self.N = self.n[0] * self.n[1] * self.n[2]
         self.tau = float(tau)
         self.eps = float(eps)
@@ -146,8 +151,12 @@ class Oracle:
         f = np.ascontiguousarray(f, dtype=np.float64)
         us = np.ascontiguousarray(us, dtype=np.float64)
         out = np.zeros(Q)
-        lib().orc_collide_cell(ctypes.byref(self.cfg), _dp(f), float(B), _dp(us), _dp(out))
+        fn = lib().orc_collide_cell_psm if self.cfg.coupling == 1 else lib().orc_collide_cell
+        fn(ctypes.byref(self.cfg), _dp(f), float(B), _dp(us), _dp(out))
         return out
+
+    def psm_weight(self, B):
+        return lib().orc_psm_weight(float(B), self.tau)
 
     # ---- fields ---------------------------------------------------------
     def equilibrium(self, rho=None, u=None):

@@ -69,6 +69,8 @@ int validate(const hlbm_config *c) {
   if (!(c->eps > 0.0) || !isfinite(c->eps)) return fail(HLBM_EINVAL, "eps must be > 0");
   if (!isfinite(c->rho_f)) return fail(HLBM_EINVAL, "rho_f not finite");
   if (c->learned != 0 && c->learned != 1) return fail(HLBM_EINVAL, "learned must be 0 or 1");
+  if (c->coupling != HLBM_COUPLING_HLBM && c->coupling != HLBM_COUPLING_PSM)
+    return fail(HLBM_EINVAL, "coupling must be HLBM_COUPLING_HLBM or HLBM_COUPLING_PSM");
   if ((c->learned || c->max_mesh_triangles > 0) &&
       !(c->learned_max_circumradius > 0 && c->learned_max_circumradius <= 27.0))
     return fail(HLBM_EINVAL, "learned_max_circumradius must be in (0, 27] (distance tables of learned or mesh shapes)");
@@ -96,6 +98,8 @@ Lattice make_lattice(const hlbm_config *c) {
   L.table_cap = 0;
   L.mesh = nullptr;
   L.mesh_nt = 0;
+  L.psm = c->coupling == HLBM_COUPLING_PSM ? 1 : 0;
+  L.tau_mh = c->tau - 0.5;
   return L;
 }
 
@@ -113,9 +117,7 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
     y.tcnt[b] = off; off += align_up((size_t)L.ntiles * sizeof(int));
     y.tlist[b] = off; off += align_up((size_t)L.ntiles * MAXC * sizeof(int));
   }
-  // momentum-exchange records: per slab (k_mea) or per tile of the bin box
-  // (evaluated by the collide kernel)
-  y.partial = off; off += align_up(np * (size_t)std::max(LMAX_CAP, REC_TILES) * 6 * sizeof(double));
+  y.partial = off; off += align_up(np * LMAX_CAP * 6 * sizeof(double));
   y.contact = off; off += align_up(np * (size_t)contact_chunks((int)np) * 3 * sizeof(double));
   y.status = off; off += 256;
   // staging: 4 FP64 planes for host transfers, or the 7-double tile records
@@ -160,9 +162,6 @@ struct hlbm_ctx {
   DevParticle *parts;
   int *order;         // particles in the momentum-exchange visiting order
   int mea_chunked;    // that order is dispatched in XCD-contiguous runs
-  int mea_fused;      // the collide kernel evaluates the next step's momentum
-                      // exchange (every particle's bin box within REC_TILES tiles)
-  bool mea_valid;     // the records it wrote describe the current state
   hlbm_particle *stage_parts;
   int *tcnt[2], *tlist[2], *status;
   int cur;            // tile-list buffer describing the current particles
@@ -233,7 +232,6 @@ int refresh_tables(hlbm_ctx *c) {
 }
 
 int mark_learned(hlbm_ctx *c) {
-  c->mea_valid = false;  // the inside test of learned particles may change
   if (!c->tables || c->n == 0) return HLBM_OK;
   LearnedModes modes;
   for (int f = 0; f < NFAM; ++f) {
@@ -307,8 +305,6 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   c->stage = (double *)(c->base + lay.stage);
   c->n = 0;
   c->mea_chunked = 0;
-  c->mea_fused = 0;
-  c->mea_valid = false;
   c->binned = false;
   c->bin_cap = 1;
   c->steps_done = 0;
@@ -443,10 +439,9 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
       if (ctx->cfg.bc[k] == HLBM_BC_WALL && !(p.pos[k] >= 0 && p.pos[k] <= nn[k]))
         return fail(HLBM_EINVAL, "particle %d: centre outside the walls", i);
     }
-    // the bin box (centre within rc + max(eps/2, 1)) spans at most
-    // floor(2 reach) + 1 cells per axis; the binning handles up to
-    // MAX_AXIS_TILES tiles of 4 cells per axis
-    const int cells = (int)floor(2.0 * (rc + std::max(0.5 * ctx->cfg.eps, 1.0))) + 2;
+    // the coupling box spans at most floor(2 (rc + eps/2)) + 1 cells per axis;
+    // the binning handles up to MAX_AXIS_TILES tiles of 4 cells per axis
+    const int cells = (int)floor(2.0 * (rc + 0.5 * ctx->cfg.eps)) + 2;
     if (cells / TY + 2 > MAX_AXIS_TILES)
       return fail(HLBM_EUNSUPPORTED, "particle %d: circumradius too large for the tile binning", i);
     const int tiles_x = std::min(ctx->L.ntx, cells / TX + 2);
@@ -512,10 +507,6 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
   ctx->mesh_particles = false;
   for (int i = 0; i < n; ++i) ctx->mesh_particles |= host[i].shape == HLBM_MESH;
   ctx->mea_chunked = chunked ? 1 : 0;
-  // the collide kernel takes over the momentum exchange when every bin box
-  // fits the per-particle records (circumradius up to about 15 cells)
-  ctx->mea_fused = 0 && cap <= REC_TILES ? 1 : 0;  // off until its parity is established
-  ctx->mea_valid = false;
   ctx->bin_cap = cap;
   ctx->lmax = lmax;
   int rc = rebin(ctx);
@@ -541,7 +532,6 @@ int hlbm_set_fields(hlbm_ctx *ctx, const double *rho, const double *u) {
   }
   HIP_TRY(launch_set_fields(ctx->cfg.precision, ctx->L, ctx->fA, drho, du, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
-  ctx->mea_valid = false;
   return HLBM_OK;
 }
 
@@ -553,20 +543,16 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
   for (int it = 0; it < nsteps; ++it) {
     const int nxt = 1 - ctx->cur;
     if (ctx->n > 0) {
-      // momentum exchange on the state of time t -- evaluated by the previous
-      // step's collide kernel when its records are valid, else here by k_mea
+      // momentum exchange on the state of time t, then Newton-Euler -> t+1 and
+      // binning of the updated particles into the other tile-list buffer
       // (slabs of 2 z-layers per workgroup for few particles, 4 for many:
-      // enough workgroups to fill the chip, few enough to amortise each) --
-      // then Newton-Euler -> t+1 and binning of the updated particles into
-      // the other tile-list buffer
+      // enough workgroups to fill the chip, few enough to amortise each)
       const int layers = ctx->n >= 1000 ? 4 : 2;
-      const bool have = ctx->mea_fused && ctx->mea_valid;
-      if (!have)
-        HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers,
-                           ctx->mea_chunked, ctx->partial, s));
+      HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers, ctx->mea_chunked,
+                         ctx->partial, s));
       HIP_TRY(launch_contact(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->contact, s));
-      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, layers, have ? 1 : 0, ctx->partial,
-                             ctx->cparams, ctx->contact, ctx->tcnt[nxt], ctx->tlist[nxt], ctx->status, s));
+      HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, layers, ctx->partial, ctx->cparams,
+                             ctx->contact, ctx->tcnt[nxt], ctx->tlist[nxt], ctx->status, s));
       int rc = refresh_tables(ctx);
       if (rc) return rc;
     }
@@ -582,10 +568,8 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
       }
       HIP_TRY(hipEventRecord(ctx->events[ctx->events_used], s));
     }
-    double *mea_out = (ctx->n > 0 && ctx->mea_fused) ? ctx->partial : nullptr;
     HIP_TRY(launch_collide(prec, ctx->L, ctx->fA, ctx->fB, ctx->parts, ctx->tcnt[use], ctx->tlist[use], clear,
-                           ctx->status, mea_out, s));
-    ctx->mea_valid = mea_out != nullptr;
+                           ctx->status, s));
     ctx->cur = use;
     if (ctx->profiling) {
       HIP_TRY(hipEventRecord(ctx->events[ctx->events_used + 1], s));
@@ -801,6 +785,39 @@ static int family(hlbm_ctx *ctx, int32_t shape, int *f) {
   return HLBM_OK;
 }
 
+// Host-side check that the device regions the training kernels of family f
+// write and read lie inside the workspace and do not overlap: parameters,
+// Adam moments, packed BF16 tiles (k_mlp_pack writes MLP_PACKED_BYTES), the
+// gradient partials of up to MLP_MAX_BLOCKS workgroups, the reduced gradient
+// and the sample pool of `samples` entries.
+static int check_training_regions(const hlbm_ctx *ctx, int f, long long samples) {
+  struct Region {
+    const char *name;
+    const char *p;
+    size_t bytes;
+  };
+  const Region r[] = {
+      {"theta", (const char *)ctx->theta[f], MLP_PARTIAL * sizeof(float)},
+      {"mom1", (const char *)ctx->mom1[f], MLP_PARTIAL * sizeof(float)},
+      {"mom2", (const char *)ctx->mom2[f], MLP_PARTIAL * sizeof(float)},
+      {"packed", (const char *)ctx->packed[f], (size_t)MLP_PACKED_BYTES},
+      {"gpart", (const char *)ctx->gpart, (size_t)MLP_MAX_BLOCKS * MLP_PARTIAL * sizeof(float)},
+      {"gout", (const char *)ctx->gout, MLP_PARTIAL * sizeof(float)},
+      {"pool", (const char *)ctx->pool, (size_t)samples * sizeof(float4)},
+  };
+  const int nr = (int)(sizeof r / sizeof r[0]);
+  const char *lo = ctx->base, *hi = ctx->base + ctx->lay.total - 256;
+  if (samples > ctx->lay.pool_cap) return fail(HLBM_EINVAL, "%lld samples above the pool capacity", samples);
+  for (int a = 0; a < nr; ++a) {
+    if (!r[a].p || r[a].p < lo || r[a].p + r[a].bytes > hi)
+      return fail(HLBM_EDEVICE, "training region %s outside the workspace", r[a].name);
+    for (int b = 0; b < a; ++b)
+      if (r[a].p < r[b].p + r[b].bytes && r[b].p < r[a].p + r[a].bytes)
+        return fail(HLBM_EDEVICE, "training regions %s and %s overlap", r[a].name, r[b].name);
+  }
+  return HLBM_OK;
+}
+
 static double circumradius_host(const hlbm_ctx *ctx, int shape, const double *prm) {
   if (shape == HLBM_ROUNDED_CUBE) return sqrt(3.0) * (prm[0] - prm[1]) + prm[1];
   if (shape == HLBM_SPHEROID) return fmax(prm[0], prm[1]);
@@ -814,6 +831,8 @@ int hlbm_mlp_set_params(hlbm_ctx *ctx, int32_t shape, const float *theta) {
   if (!theta) return fail(HLBM_EINVAL, "theta is NULL");
   for (int k = 0; k < MLP_NPARAM; ++k)
     if (!isfinite(theta[k])) return fail(HLBM_EINVAL, "theta[%d] not finite", k);
+  rc = check_training_regions(ctx, f, 0);
+  if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   HIP_TRY(hipMemcpyAsync(ctx->theta[f], theta, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(launch_fill_int((int *)ctx->mom1[f], 0, MLP_PARTIAL, ctx->stream));
@@ -821,7 +840,6 @@ int hlbm_mlp_set_params(hlbm_ctx *ctx, int32_t shape, const float *theta) {
   HIP_TRY(mlp_pack(ctx->theta[f], ctx->packed[f], ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   ctx->has_params[f] = 1;
-  ctx->mea_valid = false;  // distance tables of learned particles change
   return refresh_tables(ctx);
 }
 
@@ -859,6 +877,8 @@ int hlbm_mlp_gradient(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts
   if (n < 1 || n > ctx->lay.pool_cap) return fail(HLBM_EINVAL, "n outside [1, %lld]", ctx->lay.pool_cap);
   if (!pts || !target || !grad) return fail(HLBM_EINVAL, "NULL buffer");
   if (!ctx->has_params[f]) return fail(HLBM_ESTATE, "no parameters for this family");
+  rc = check_training_regions(ctx, f, n);
+  if (rc) return rc;
   std::vector<float4> smp(n);
   for (int k = 0; k < n; ++k)
     smp[k] = make_float4((float)pts[3 * k], (float)pts[3 * k + 1], (float)pts[3 * k + 2], (float)target[k]);
@@ -884,6 +904,8 @@ int hlbm_mlp_train_step(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *p
   if (!pts || !target) return fail(HLBM_EINVAL, "NULL buffer");
   if (!(lr > 0.0) || !isfinite(lr) || step < 1) return fail(HLBM_EINVAL, "need lr > 0 and step >= 1");
   if (!ctx->has_params[f]) return fail(HLBM_ESTATE, "no parameters for this family");
+  rc = check_training_regions(ctx, f, n);
+  if (rc) return rc;
   std::vector<float4> smp(n);
   for (int k = 0; k < n; ++k)
     smp[k] = make_float4((float)pts[3 * k], (float)pts[3 * k + 1], (float)pts[3 * k + 2], (float)target[k]);
@@ -900,7 +922,6 @@ int hlbm_mlp_train_step(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *p
   if (grad)
     for (int k = 0; k < MLP_NPARAM; ++k) grad[k] = g[k];
   if (loss) *loss = g[MLP_NPARAM] / n;
-  ctx->mea_valid = false;  // distance tables of learned particles change
   return refresh_tables(ctx);
 }
 
@@ -950,6 +971,8 @@ int hlbm_train_indicator(hlbm_ctx *ctx, int32_t shape, const double *param, cons
   if (!(o->lr > 0 && o->lr_final > 0 && o->box > 0 && o->band > 0 && o->clip >= o->band &&
         o->band_share >= 0 && o->band_share <= 1))
     return fail(HLBM_EINVAL, "bad learning rate / box / band / clip");
+  rc = check_training_regions(ctx, f, (long long)o->samples + o->holdout);
+  if (rc) return rc;
   const auto t0 = std::chrono::steady_clock::now();
   const double Rc = circumradius_host(ctx, shape, param);
   const double p0 = param[0] / Rc, p1 = param[1] / Rc;

@@ -74,6 +74,8 @@ struct Lattice {
   long long table_cap;  // floats per particle table
   const float4 *mesh;   // triangles of the mesh shape: 3 vertices each (unit scale)
   int mesh_nt;          // number of triangles (0: no mesh)
+  int psm;              // coupling: 0 exact-difference source (HLBM), 1 partially saturated collision
+  double tau_mh;        // tau - 1/2
 };
 
 // Particle record on the device (FP64).  The first block mirrors the public
@@ -88,17 +90,7 @@ struct DevParticle {
   int shape, flags;
   int lo[3], hi[3];  // cells that can have B > 0 (centre within rc + eps/2), unwrapped
   int learned;       // distance table: 0 none, 1 learned (network), 2 exact (mesh)
-  // bin box: cells within rc + max(eps/2, 1) of the centre (unwrapped), the
-  // union of the coupling box and the cells whose momentum-exchange terms the
-  // particle collects (an inside cell or a neighbour of one); the particle is
-  // listed in every tile the bin box touches
-  int blo[3], bhi[3];
-  int nrec;          // tiles the bin box touches (records of the fused exchange)
 };
-
-// Records of the momentum exchange evaluated inside the collide kernel: one
-// per (particle, tile of its bin box), at most REC_TILES tiles.
-constexpr int REC_TILES = 256;
 
 // Tiles touched by a cell range along one axis (wrapped on periodic axes),
 // in increasing cell order; returns the count (<= MAX_AXIS_TILES).  Steps from
@@ -118,31 +110,6 @@ __device__ inline int axis_tiles(int lo, int hi, int n, int periodic, int tsize,
     c += min((t + 1) * tsize, n) - w;  // first cell of the next tile
   }
   return cnt;
-}
-
-// Position of tile t among the tiles axis_tiles lists for [lo, hi] (-1 if
-// absent), and their count in *cnt.
-__device__ inline int axis_tile_index(int lo, int hi, int n, int periodic, int tsize, int t, int &cnt) {
-  int tl[MAX_AXIS_TILES];
-  cnt = axis_tiles(lo, hi, n, periodic, tsize, tl);
-  int pos = -1;
-  for (int k = 0; k < cnt; ++k)
-    if (tl[k] == t) pos = k;
-  return pos;
-}
-
-// The coordinate of cell v unwrapped into the (possibly wrapping) range
-// [lo, hi] of an axis: u = v + k n with lo <= u <= hi; false if none.
-__device__ inline bool unwrap_into(int v, int lo, int hi, int n, int periodic, int &u) {
-  if (!periodic) {
-    u = v;
-    return v >= lo && v <= hi;
-  }
-  int d = v - lo;
-  d %= n;
-  if (d < 0) d += n;
-  u = lo + d;
-  return u <= hi;
 }
 
 // Offset of a cell inside a particle's coupling box (wrapped on periodic axes);

@@ -66,9 +66,12 @@ __device__ inline void cell_observables(const Lattice &L, const typename ST::S *
   for (int k = 0; k < 3; ++k) u[k] = j[k] / rho;
   const double s0 = (double)S0;
   Bc = s0 < 1.0 ? s0 : 1.0;
+  // the velocity change of the step's coupling per unit density: weight B
+  // (exact-difference source) or B_n (partially saturated collision)
+  const double Bw = L.psm ? Bc * L.tau_mh / ((1.0 - Bc) + L.tau_mh) : Bc;
   for (int k = 0; k < 3; ++k) {
     const double us = s0 > 0.0 ? (double)S1[k] / s0 : 0.0;
-    const double du = Bc * (us - u[k]) + (1.0 - Bc) * L.af[k];
+    const double du = Bw * (us - u[k]) + (1.0 - Bw) * L.af[k];
     up[k] = u[k] + 0.5 * du;
   }
 }

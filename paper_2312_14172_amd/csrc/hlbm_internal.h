@@ -43,17 +43,11 @@ __host__ __device__ inline int contact_chunks(int n) {
 // per-chunk contact forces out[chunk][n][3] from the state before the EoM
 hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c, double *out,
                           hipStream_t s);
-// tile_mode: the records come from the collide kernel (per tile of the bin
-// box, REC_TILES per particle), else from k_mea (per slab, lmax per particle)
-hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, int tile_mode,
-                          const double *partial, const ContactParams &c, const double *contact, int *tcnt, int *tlist,
-                          int *status, hipStream_t s);
-// mea_out: if not NULL, the kernel also evaluates the next step's momentum
-// exchange on the populations it writes and the particles it couples, into
-// records mea_out[pid][tile][6]
-hipError_t launch_collide(int prec, const Lattice &L, const void *A, void *B, const DevParticle *parts,
-                          const int *tcnt, const int *tlist, int *tcnt_clear, int *status, double *mea_out,
+hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, const double *partial,
+                          const ContactParams &c, const double *contact, int *tcnt, int *tlist, int *status,
                           hipStream_t s);
+hipError_t launch_collide(int prec, const Lattice &L, const void *A, void *B, const DevParticle *parts,
+                          const int *tcnt, const int *tlist, int *tcnt_clear, int *status, hipStream_t s);
 hipError_t launch_set_fields(int prec, const Lattice &L, void *A, const double *rho, const double *u,
                              hipStream_t s);
 hipError_t launch_fields(int prec, const Lattice &L, const void *A, const DevParticle *parts,

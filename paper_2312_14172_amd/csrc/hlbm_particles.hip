@@ -61,17 +61,9 @@ __device__ inline void cell_box(const Lattice &L, const double *X, double reach,
   }
 }
 
-// Coupling box: the cells that can have B > 0 (centre within rc + eps/2);
-// bin box: the coupling box and every cell within one cell of the particle's
-// inside cells (centre within rc + 1), i.e. within rc + max(eps/2, 1), and the
-// number of tiles it touches.
+// Coupling box: the cells that can have B > 0 (centre within rc + eps/2).
 __device__ inline void particle_boxes(const Lattice &L, DevParticle &p) {
   cell_box(L, p.X, p.rc + 0.5 * L.eps + 1e-9, p.lo, p.hi);
-  cell_box(L, p.X, p.rc + fmax(0.5 * L.eps, 1.0) + 1e-9, p.blo, p.bhi);
-  int t[MAX_AXIS_TILES];
-  p.nrec = axis_tiles(p.blo[0], p.bhi[0], L.nx, !L.bc[0], TX, t) *
-           axis_tiles(p.blo[1], p.bhi[1], L.ny, !L.bc[1], TY, t) *
-           axis_tiles(p.blo[2], p.bhi[2], L.nz, !L.bc[2], TZ, t);
 }
 
 __device__ inline void derive(const Lattice &L, DevParticle &p) {
@@ -121,16 +113,16 @@ __global__ void k_fill_int(int *p, int v, int n) {
   if (i < n) p[i] = v;
 }
 
-// One thread per (particle, tile of its bin box): append the particle to the
-// tile's list.  grid = (ceil(cap / 64), n).
+// One thread per (particle, tile of its coupling box): append the particle to
+// the tile's list.  grid = (ceil(cap / 64), n).
 __global__ void k_bin(Lattice L, const DevParticle *parts, int *tcnt, int *tlist, int *status) {
   const int pid = blockIdx.y;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const DevParticle &p = parts[pid];
   int tx[MAX_AXIS_TILES], ty[MAX_AXIS_TILES], tz[MAX_AXIS_TILES];
-  const int cx = axis_tiles(p.blo[0], p.bhi[0], L.nx, !L.bc[0], TX, tx);
-  const int cy = axis_tiles(p.blo[1], p.bhi[1], L.ny, !L.bc[1], TY, ty);
-  const int cz = axis_tiles(p.blo[2], p.bhi[2], L.nz, !L.bc[2], TZ, tz);
+  const int cx = axis_tiles(p.lo[0], p.hi[0], L.nx, !L.bc[0], TX, tx);
+  const int cy = axis_tiles(p.lo[1], p.hi[1], L.ny, !L.bc[1], TY, ty);
+  const int cz = axis_tiles(p.lo[2], p.hi[2], L.nz, !L.bc[2], TZ, tz);
   if (k >= cx * cy * cz) return;
   const int a = k % cx, b = (k / cx) % cy, c = k / (cx * cy);
   const int t = tx[a] + L.ntx * (ty[b] + L.nty * tz[c]);
@@ -515,20 +507,17 @@ __device__ inline void contact_walls(const Lattice &L, const DevParticle &p, con
 // lists of its new coupling box.
 template <bool CONTACT>
 __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restrict__ parts, int n, int lmax,
-                                                int layers, int tile_mode, const double *__restrict__ partial,
-                                                ContactParams c, const double *__restrict__ contact, int *tcnt,
-                                                int *tlist, int *status) {
+                                                int layers, const double *__restrict__ partial, ContactParams c,
+                                                const double *__restrict__ contact, int *tcnt, int *tlist,
+                                                int *status) {
   __shared__ int ts[3][MAX_AXIS_TILES];
   __shared__ int tn[3];
   const int pid = blockIdx.x;
   const int t = threadIdx.x;
-  // records of the momentum exchange: per tile of the bin box from the
-  // collide kernel (tile_mode), else per slab from k_mea.  The first ones are
-  // loaded before their count is known (every slot up to the largest count
-  // exists), so the loads overlap the box computation.
-  const size_t stride = tile_mode ? (size_t)REC_TILES : (size_t)lmax;
-  const double *src = partial + (size_t)pid * stride * 6;
-  const int nmax = tile_mode ? REC_TILES : (lmax + layers - 1) / layers;
+  // the slab records are loaded before their count is known (every slot up
+  // to the largest count exists), so the loads overlap the box computation
+  const double *src = partial + (size_t)pid * lmax * 6;
+  const int nmax = (lmax + layers - 1) / layers;
   double acc[6] = {0, 0, 0, 0, 0, 0};
   double first[6];
   const bool have = t < nmax;
@@ -538,14 +527,9 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
   double fc[3] = {0.0, 0.0, 0.0};
   if (CONTACT && t < contact_chunks(n))
     for (int a = 0; a < 3; ++a) fc[a] = contact[((size_t)t * n + pid) * 3 + a];
-  int nrec;
-  if (tile_mode) {
-    nrec = min(parts[pid].nrec, REC_TILES);
-  } else {
-    int lo[3], hi[3];
-    cell_box(L, parts[pid].X, parts[pid].rc + 1e-9, lo, hi);
-    nrec = mea_slabs(lo[2], hi[2], layers);
-  }
+  int lo[3], hi[3];
+  cell_box(L, parts[pid].X, parts[pid].rc + 1e-9, lo, hi);
+  const int nrec = mea_slabs(lo[2], hi[2], layers);
   if (have && t < nrec)
     for (int k = 0; k < 6; ++k) acc[k] = first[k];
   for (int r = t + 64; r < nrec; r += 64)
@@ -562,9 +546,9 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
       advance_particle(L, p, acc, nullptr, status);
     }
     parts[pid] = p;
-    tn[0] = axis_tiles(p.blo[0], p.bhi[0], L.nx, !L.bc[0], TX, ts[0]);
-    tn[1] = axis_tiles(p.blo[1], p.bhi[1], L.ny, !L.bc[1], TY, ts[1]);
-    tn[2] = axis_tiles(p.blo[2], p.bhi[2], L.nz, !L.bc[2], TZ, ts[2]);
+    tn[0] = axis_tiles(p.lo[0], p.hi[0], L.nx, !L.bc[0], TX, ts[0]);
+    tn[1] = axis_tiles(p.lo[1], p.hi[1], L.ny, !L.bc[1], TY, ts[1]);
+    tn[2] = axis_tiles(p.lo[2], p.hi[2], L.nz, !L.bc[2], TZ, ts[2]);
   }
   __syncthreads();
   const int cx = tn[0], cy = tn[1], cz = tn[2];
@@ -635,16 +619,16 @@ hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, con
   return hipGetLastError();
 }
 
-hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, int tile_mode,
-                          const double *partial, const ContactParams &c, const double *contact, int *tcnt, int *tlist,
-                          int *status, hipStream_t s) {
+hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, const double *partial,
+                          const ContactParams &c, const double *contact, int *tcnt, int *tlist, int *status,
+                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (c.on)
-    hipLaunchKernelGGL(k_eom_bin<true>, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, tile_mode, partial, c,
-                       contact, tcnt, tlist, status);
+    hipLaunchKernelGGL(k_eom_bin<true>, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, partial, c, contact, tcnt,
+                       tlist, status);
   else
-    hipLaunchKernelGGL(k_eom_bin<false>, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, tile_mode, partial, c,
-                       contact, tcnt, tlist, status);
+    hipLaunchKernelGGL(k_eom_bin<false>, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, partial, c, contact, tcnt,
+                       tlist, status);
   return hipGetLastError();
 }
 

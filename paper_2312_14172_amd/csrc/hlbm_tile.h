@@ -92,9 +92,6 @@ struct Cand {
   int shape;
   long long tab; // first table entry of a learned particle, -1 for the exact path
   int tsx, tsy;  // coupling-box extents (table strides)
-  int pid;       // particle index
-  int rec;       // this tile's position among the tiles of the particle's bin box
-  int blo[3], bhi[3];  // bin box (unwrapped)
 };
 
 template <typename G>
@@ -145,18 +142,6 @@ __device__ inline void load_candidates(const Lattice &L, const DevParticle *part
     c.tab = (p.learned && L.tables) ? (long long)id * L.table_cap : -1;
     c.tsx = p.hi[0] - p.lo[0] + 1;
     c.tsy = p.hi[1] - p.lo[1] + 1;
-    c.pid = id;
-    const int tx = tile % L.ntx, ty = (tile / L.ntx) % L.nty, tz = tile / (L.ntx * L.nty);
-    int cx, cy;
-    const int a = axis_tile_index(p.blo[0], p.bhi[0], L.nx, !L.bc[0], TX, tx, cx);
-    const int b = axis_tile_index(p.blo[1], p.bhi[1], L.ny, !L.bc[1], TY, ty, cy);
-    int cz;
-    const int e = axis_tile_index(p.blo[2], p.bhi[2], L.nz, !L.bc[2], TZ, tz, cz);
-    c.rec = a + cx * (b + cy * e);
-    for (int k = 0; k < 3; ++k) {
-      c.blo[k] = p.blo[k];
-      c.bhi[k] = p.bhi[k];
-    }
   }
   __syncthreads();
 }

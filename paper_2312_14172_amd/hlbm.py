@@ -41,7 +41,7 @@ class hlbm_config(ctypes.Structure):
                 ("gravity", ctypes.c_double * 3), ("fluid_accel", ctypes.c_double * 3),
                 ("stream", ctypes.c_void_p), ("learned", ctypes.c_int32),
                 ("learned_samples", ctypes.c_int32), ("learned_max_circumradius", ctypes.c_double),
-                ("max_mesh_triangles", ctypes.c_int32)]
+                ("max_mesh_triangles", ctypes.c_int32), ("coupling", ctypes.c_int32)]
 
 
 class hlbm_train_opts(ctypes.Structure):
@@ -125,9 +125,12 @@ def _check(rc):
         raise HLBMError(rc, lib().hlbm_last_error().decode())
 
 
+COUPLINGS = {"hlbm": 0, "psm": 1}
+
+
 def make_config(n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps=0.5, rho_f=1.0,
                 gravity=(0.0, 0.0, 0.0), fluid_accel=(0.0, 0.0, 0.0), stream=None,
-                learned_max_circumradius=0.0, learned_samples=0, max_mesh_triangles=0):
+                learned_max_circumradius=0.0, learned_samples=0, max_mesh_triangles=0, coupling="hlbm"):
     c = hlbm_config()
     c.nx, c.ny, c.nz = (int(v) for v in n)
     c.bc = (ctypes.c_int32 * 3)(*[int(b) for b in bc])
@@ -141,6 +144,7 @@ def make_config(n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps
     c.learned_samples = int(learned_samples)
     c.learned_max_circumradius = float(learned_max_circumradius)
     c.max_mesh_triangles = int(max_mesh_triangles)
+    c.coupling = COUPLINGS[coupling] if isinstance(coupling, str) else int(coupling)
     return c
 
 
@@ -158,7 +162,8 @@ class Simulation:
 
     def __init__(self, n, bc=(0, 0, 0), tau=0.8, precision="fp64", max_particles=0, eps=0.5,
                  rho_f=1.0, gravity=(0.0, 0.0, 0.0), fluid_accel=(0.0, 0.0, 0.0), device=None,
-                 stream=None, learned_max_circumradius=0.0, learned_samples=0, max_mesh_triangles=0):
+                 stream=None, learned_max_circumradius=0.0, learned_samples=0, max_mesh_triangles=0,
+                 coupling="hlbm"):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -167,7 +172,7 @@ class Simulation:
         self.N = self.n[0] * self.n[1] * self.n[2]
         self.cfg = make_config(n, bc, tau, precision, max_particles, eps, rho_f, gravity,
                                fluid_accel, ctypes.c_void_p(self.stream.cuda_stream),
-                               learned_max_circumradius, learned_samples, max_mesh_triangles)
+                               learned_max_circumradius, learned_samples, max_mesh_triangles, coupling)
         nbytes = ctypes.c_size_t(0)
         _check(lib().hlbm_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)

@@ -29,9 +29,10 @@ def test_library_exports_every_declared_function():
 def test_particle_record_layout_matches_header():
     # 21 doubles + 2 int32 = 176 bytes, field order as declared
     assert H.HLBM_PARTICLE.itemsize == 176
-    # 8 int32, 9 doubles, the stream pointer, 2 int32, 1 double, 1 int32 (+ 4 padding)
+    # 8 int32, 9 doubles, the stream pointer, 2 int32, 1 double, 2 int32
     assert ctypes.sizeof(H.hlbm_config) == 4 * 8 + 8 * 9 + 8 + 4 + 4 + 8 + 4 + 4
     assert H.hlbm_config.max_mesh_triangles.offset == 128
+    assert H.hlbm_config.coupling.offset == 132
 
 
 def _size(**kw):
