@@ -355,6 +355,21 @@ int hlbm_train_indicator(hlbm_ctx *ctx, int32_t shape, const double *param, cons
  * the family whose aspect differs from the trained one keep the exact path. */
 int hlbm_set_indicator(hlbm_ctx *ctx, int32_t shape, int32_t mode);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the gradient of
+ * hlbm_mlp_gradient without a context.  All pointers are device memory on
+ * the current device: d_theta[HLBM_MLP_NPARAM] the FP32 parameters,
+ * d_samples[n][4] FP32 (x, y, z, target) in normalised units, d_grad
+ * receives HLBM_MLP_NPARAM + 1 floats: the gradient of the mean-squared loss
+ * mean_s (net(x_s) - t_s)^2, then the sum of squared errors.  The work is
+ * queued on stream (hipStream_t, NULL = default) and not waited for; nothing
+ * is allocated or freed.  The working memory is a fixed array of 2.2 MB per
+ * GPU inside the library, so n is limited to 2048 (HLBM_EUNSUPPORTED above);
+ * the results equal hlbm_mlp_gradient's for the same inputs (the same
+ * kernels and partition).  Calls that overlap on one GPU (on different
+ * streams or threads) race on that array.  HLBM_EINVAL for NULL pointers. */
+int hlbm_mlp_gradient_noalloc(const float *d_theta, int32_t n, const float *d_samples, float *d_grad, void *stream);
+
 /* Number of particles currently held. */
 int hlbm_num_particles(const hlbm_ctx *ctx, int32_t *n);
 

@@ -14,6 +14,7 @@
 #include "hlbm_mlp.h"
 
 #include <chrono>
+#include <mutex>
 
 using namespace hlbm;
 
@@ -1055,3 +1056,68 @@ int hlbm_set_indicator(hlbm_ctx *ctx, int32_t shape, int32_t mode) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The surrogate-network gradient without a context and without allocation.
+// Its working memory (the packed BF16 weight tiles and the per-workgroup
+// gradient partials) is a fixed device array of this library, held by every
+// GPU the library runs on until the process ends.  Host code never passes
+// the array's name to a kernel: each device's copy is found once, with that
+// device current, by hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+namespace {
+// samples per call: at most NOALLOC_BLOCKS gradient workgroups of 32 samples,
+// the partition hlbm_mlp_gradient takes for these sizes
+constexpr int NOALLOC_BLOCKS = 64;
+constexpr int NOALLOC_MAX_SAMPLES = NOALLOC_BLOCKS * 32;
+constexpr size_t NOALLOC_PACKED_OFF = 0;
+constexpr size_t NOALLOC_PARTIAL_OFF = ((size_t)MLP_PACKED_BYTES + 255) / 256 * 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_PARTIAL_OFF + (size_t)NOALLOC_BLOCKS * MLP_PARTIAL * sizeof(float);
+constexpr int NOALLOC_MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+std::mutex g_scratch_mutex;
+unsigned char *g_scratch[NOALLOC_MAX_DEVICES] = {};
+
+// The current device's copy of the scratch array (found on first use).
+int scratch_for_current_device(unsigned char **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(HLBM_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(HLBM_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    }
+    g_scratch[dev] = (unsigned char *)p;
+  }
+  *out = g_scratch[dev];
+  return HLBM_OK;
+}
+}  // namespace
+
+extern "C" int hlbm_mlp_gradient_noalloc(const float *d_theta, int32_t n, const float *d_samples, float *d_grad,
+                                         void *stream) {
+  if (!d_theta || !d_samples || !d_grad) return fail(HLBM_EINVAL, "NULL argument");
+  if (n < 1 || n > NOALLOC_MAX_SAMPLES)
+    return fail(HLBM_EUNSUPPORTED, "n = %d outside [1, %d] (fixed scratch)", n, NOALLOC_MAX_SAMPLES);
+  const int nb = mlp_grad_blocks(n, MLP_MAX_BLOCKS);
+  if (nb > NOALLOC_BLOCKS) return fail(HLBM_EUNSUPPORTED, "n = %d needs %d gradient workgroups", n, nb);
+  unsigned char *base = nullptr;
+  int rc = scratch_for_current_device(&base);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  __bf16 *packed = (__bf16 *)(base + NOALLOC_PACKED_OFF);
+  float *partial = (float *)(base + NOALLOC_PARTIAL_OFF);
+  HIP_TRY(mlp_pack(d_theta, packed, s));
+  HIP_TRY(mlp_grad(d_theta, packed, (const float4 *)d_samples, n, MLP_MAX_BLOCKS, 2.0f / n, partial, s));
+  // the reduction alone (no Adam step): parameters and moments are not touched
+  HIP_TRY(mlp_reduce_adam(const_cast<float *>(d_theta), nullptr, nullptr, partial, nb, d_grad, 0, 0.f, 1, s));
+  return HLBM_OK;
+}

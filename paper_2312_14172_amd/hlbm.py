@@ -28,7 +28,8 @@ EXPORTED = ["hlbm_workspace_size", "hlbm_init", "hlbm_destroy", "hlbm_set_partic
             "hlbm_get_fields", "hlbm_get_mean_velocity",
             "hlbm_num_particles", "hlbm_profile_begin", "hlbm_profile_end", "hlbm_mlp_set_params",
             "hlbm_mlp_get_params", "hlbm_mlp_eval", "hlbm_mlp_gradient", "hlbm_train_indicator",
-            "hlbm_set_indicator", "hlbm_mlp_train_step", "hlbm_mlp_samples", "hlbm_last_error"]
+            "hlbm_set_indicator", "hlbm_mlp_train_step", "hlbm_mlp_samples", "hlbm_mlp_gradient_noalloc",
+            "hlbm_last_error"]
 MLP_NPARAM = 8641
 INDICATOR_EXACT, INDICATOR_LEARNED = 0, 1
 
@@ -109,6 +110,7 @@ def lib():
         L.hlbm_train_indicator.argtypes = [vp, i32, vp, ctypes.POINTER(hlbm_train_opts),
                                            ctypes.POINTER(hlbm_train_report)]
         L.hlbm_set_indicator.argtypes = [vp, i32, i32]
+        L.hlbm_mlp_gradient_noalloc.argtypes = [vp, i32, vp, vp, vp]
         L.hlbm_mlp_train_step.argtypes = [vp, i32, i32, vp, vp, ctypes.c_double, i32, vp, vp]
         L.hlbm_mlp_samples.argtypes = [vp, i32, vp, ctypes.c_uint64, i32, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, vp]
@@ -155,6 +157,21 @@ def to_particle_records(particles) -> np.ndarray:
     for name in HLBM_PARTICLE.names:
         out[name] = particles[name]
     return out
+
+
+def mlp_gradient_noalloc(theta, samples, grad, stream=None):
+    """hlbm_mlp_gradient_noalloc on device tensors: theta [8641] float32,
+    samples [n, 4] float32 (x, y, z, target), grad [8642] float32 (gradient,
+    then the sum of squared errors); queued on the stream (torch's current
+    one by default), not synchronised."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(theta.device)
+    for t in (theta, samples, grad):
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    assert theta.numel() == MLP_NPARAM and grad.numel() == MLP_NPARAM + 1 and samples.shape[-1] == 4
+    _check(lib().hlbm_mlp_gradient_noalloc(ctypes.c_void_p(theta.data_ptr()), int(samples.shape[0]),
+                                           ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                           ctypes.c_void_p(s.cuda_stream)))
 
 
 class Simulation:
