@@ -188,47 +188,74 @@ __device__ inline S mea_load(const S *__restrict__ plane, unsigned cell) {
 
 // One inside cell's F_h, added as -F_h and -(x_b - X) x F_h.  With the stored
 // relative deviations s = K (f - w) / w of f_i(x_b + c_i) and f_opp(i)(x_b):
-//   (c - u) f_in + (c + u) f_out = c w (2 + (s_in + s_out) / K) - u w (s_in - s_out) / K.
+//   (c - u) f_in + (c + u) f_out = c w (2 + (s_in + s_out) / K) - u w (s_in - s_out) / K,
+// so over the kept directions (not past a wall), with w_i = w36_i / 36
+// (w36 = 2 along the axes, 1 along the diagonals):
+//   F_h = (2 sum c_i w36_i + a / K - u b / K) / 36,
+//   a = sum c_i w36_i (s_in + s_out),  b = sum w36_i (s_in - s_out).
+// The weight sum is an exact integer (minus the skipped directions' share of
+// sum_i c_i w36_i = 0); a and b, sums of the small stored deviations, are
+// formed in the arithmetic precision T (FP64 for FP64 storage), and
+// everything from them on in FP64.  Cells off the lattice boundary take the
+// neighbour index as cell + a constant offset per direction.
 template <class ST, bool O32>
 __device__ inline void mea_accumulate(const Lattice &L, const typename ST::S *__restrict__ A, const int *c,
                                       const double *d, const double *U, const double *W, double *F, double *T) {
   using S = typename ST::S;
+  using TT = typename ST::T;
+  const unsigned nxu = (unsigned)L.nx, sxy = (unsigned)L.nx * (unsigned)L.ny;
+  const unsigned cell = (unsigned)c[0] + nxu * (unsigned)c[1] + sxy * (unsigned)c[2];
+  const bool inner = c[0] > 0 && c[0] < L.nx - 1 && c[1] > 0 && c[1] < L.ny - 1 && c[2] > 0 && c[2] < L.nz - 1;
+  int xm = c[0] - 1, xp = c[0] + 1, ym = c[1] - 1, yp = c[1] + 1, zm = c[2] - 1, zp = c[2] + 1;
+  bool okxm = true, okxp = true, okym = true, okyp = true, okzm = true, okzp = true;
+  if (!inner) {
+    xm = c[0] == 0 ? L.nx - 1 : xm; xp = c[0] == L.nx - 1 ? 0 : xp;
+    ym = c[1] == 0 ? L.ny - 1 : ym; yp = c[1] == L.ny - 1 ? 0 : yp;
+    zm = c[2] == 0 ? L.nz - 1 : zm; zp = c[2] == L.nz - 1 ? 0 : zp;
+    okxm = !(L.bc[0] && c[0] == 0); okxp = !(L.bc[0] && c[0] == L.nx - 1);
+    okym = !(L.bc[1] && c[1] == 0); okyp = !(L.bc[1] && c[1] == L.ny - 1);
+    okzm = !(L.bc[2] && c[2] == 0); okzp = !(L.bc[2] && c[2] == L.nz - 1);
+  }
+  TT a0 = 0, a1 = 0, a2 = 0, b = 0;
+  int k0 = 0, k1 = 0, k2 = 0;  // sum over skipped directions of c_i w36_i
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int w36 = i <= 6 ? 2 : 1;
+    unsigned nb;
+    bool ok;
+    if (inner) {
+      nb = cell + (unsigned)(kCX[i] + L.nx * kCY[i] + (int)sxy * kCZ[i]);
+      ok = true;
+    } else {
+      const int ex = kCX[i] == 1 ? xp : (kCX[i] == -1 ? xm : c[0]);
+      const int ey = kCY[i] == 1 ? yp : (kCY[i] == -1 ? ym : c[1]);
+      const int ez = kCZ[i] == 1 ? zp : (kCZ[i] == -1 ? zm : c[2]);
+      ok = (kCX[i] == 1 ? okxp : (kCX[i] == -1 ? okxm : true)) &&
+           (kCY[i] == 1 ? okyp : (kCY[i] == -1 ? okym : true)) &&
+           (kCZ[i] == 1 ? okzp : (kCZ[i] == -1 ? okzm : true));
+      nb = (unsigned)ex + nxu * (unsigned)ey + sxy * (unsigned)ez;
+    }
+    const S *__restrict__ Ain = A + (size_t)i * (size_t)L.N;
+    const S *__restrict__ Aout = A + (size_t)opp(i) * (size_t)L.N;
+    const TT sin_ = ST::dec(mea_load<O32>(Ain, cell));
+    const TT sout = ST::dec(mea_load<O32>(Aout, nb));
+    const TT sp = ok ? sin_ + sout : (TT)0, sm = ok ? sin_ - sout : (TT)0;
+    if (kCX[i]) a0 += (TT)(kCX[i] * w36) * sp;
+    if (kCY[i]) a1 += (TT)(kCY[i] * w36) * sp;
+    if (kCZ[i]) a2 += (TT)(kCZ[i] * w36) * sp;
+    b += (TT)w36 * sm;
+    if (!ok) { k0 += kCX[i] * w36; k1 += kCY[i] * w36; k2 += kCZ[i] * w36; }
+  }
   const double upx = U[0] + W[1] * d[2] - W[2] * d[1];
   const double upy = U[1] + W[2] * d[0] - W[0] * d[2];
   const double upz = U[2] + W[0] * d[1] - W[1] * d[0];
-  const unsigned sxy = (unsigned)L.nx * (unsigned)L.ny;
-  const unsigned cell = (unsigned)c[0] + (unsigned)L.nx * (unsigned)c[1] + sxy * (unsigned)c[2];
-  const int xm = c[0] == 0 ? L.nx - 1 : c[0] - 1, xp = c[0] == L.nx - 1 ? 0 : c[0] + 1;
-  const int ym = c[1] == 0 ? L.ny - 1 : c[1] - 1, yp = c[1] == L.ny - 1 ? 0 : c[1] + 1;
-  const int zm = c[2] == 0 ? L.nz - 1 : c[2] - 1, zp = c[2] == L.nz - 1 ? 0 : c[2] + 1;
-  const bool okxm = !(L.bc[0] && c[0] == 0), okxp = !(L.bc[0] && c[0] == L.nx - 1);
-  const bool okym = !(L.bc[1] && c[1] == 0), okyp = !(L.bc[1] && c[1] == L.ny - 1);
-  const bool okzm = !(L.bc[2] && c[2] == 0), okzp = !(L.bc[2] && c[2] == L.nz - 1);
-  const double invK = 1.0 / (double)ST::K();
-  double h[3] = {0, 0, 0};
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const int ex = kCX[i] == 1 ? xp : (kCX[i] == -1 ? xm : c[0]);
-    const int ey = kCY[i] == 1 ? yp : (kCY[i] == -1 ? ym : c[1]);
-    const int ez = kCZ[i] == 1 ? zp : (kCZ[i] == -1 ? zm : c[2]);
-    const bool ok = (kCX[i] == 1 ? okxp : (kCX[i] == -1 ? okxm : true)) &&
-                    (kCY[i] == 1 ? okyp : (kCY[i] == -1 ? okym : true)) &&
-                    (kCZ[i] == 1 ? okzp : (kCZ[i] == -1 ? okzm : true));
-    const unsigned nb = (unsigned)ex + (unsigned)L.nx * (unsigned)ey + sxy * (unsigned)ez;
-    const S *__restrict__ Ain = A + (size_t)i * (size_t)L.N;
-    const S *__restrict__ Aout = A + (size_t)opp(i) * (size_t)L.N;
-    const double sin_ = (double)ST::dec(mea_load<O32>(Ain, cell));
-    const double sout = (double)ST::dec(mea_load<O32>(Aout, nb));
-    const double w = ok ? wgt(i) : 0.0;
-    const double sum = w * (2.0 + (sin_ + sout) * invK);
-    const double dif = w * ((sin_ - sout) * invK);
-    if (kCX[i] != 0) h[0] += kCX[i] > 0 ? sum : -sum;
-    if (kCY[i] != 0) h[1] += kCY[i] > 0 ? sum : -sum;
-    if (kCZ[i] != 0) h[2] += kCZ[i] > 0 ? sum : -sum;
-    h[0] -= upx * dif;
-    h[1] -= upy * dif;
-    h[2] -= upz * dif;
-  }
+  const double invK = 1.0 / (double)ST::K(), i36 = 1.0 / 36.0;
+  const double bk = (double)b * invK;
+  // kept directions: sum c w36 = -(skipped share)
+  double h[3];
+  h[0] = ((double)(-2 * k0) + (double)a0 * invK - upx * bk) * i36;
+  h[1] = ((double)(-2 * k1) + (double)a1 * invK - upy * bk) * i36;
+  h[2] = ((double)(-2 * k2) + (double)a2 * invK - upz * bk) * i36;
   F[0] -= h[0]; F[1] -= h[1]; F[2] -= h[2];
   cross_sub(d, h, T);
 }
