@@ -52,6 +52,7 @@ struct Layout {
   size_t fA, fB, parts, order, stage_parts, tcnt[2], tlist[2], partial, contact, status, stage, total;
   // learned indicator (cfg.learned)
   size_t theta[NFAM], mom1[NFAM], mom2[NFAM], packed[NFAM], gpart, gout, pool, epts, eout, tables, mesh;
+  size_t band[NFAM];  // band grids (learned or mesh shapes)
   long long pool_cap, table_cap;
 };
 
@@ -76,6 +77,13 @@ int validate(const hlbm_config *c) {
       !(c->learned_max_circumradius > 0 && c->learned_max_circumradius <= 27.0))
     return fail(HLBM_EINVAL, "learned_max_circumradius must be in (0, 27] (distance tables of learned or mesh shapes)");
   if (c->learned && c->learned_samples < 0) return fail(HLBM_EINVAL, "learned_samples < 0");
+  if (c->learned || c->max_mesh_triangles > 0) {
+    // the table kernels index a box with FP32 quotients, exact below 2^22 cells
+    const double side = floor(2.0 * (c->learned_max_circumradius + 0.5 * c->eps)) + 2;
+    if (side * side * side >= 4194304.0)
+      return fail(HLBM_EUNSUPPORTED, "distance tables of %.0f^3 cells: learned_max_circumradius + eps/2 too large",
+                  side);
+  }
   for (int k = 0; k < 3; ++k)
     if (!isfinite(c->gravity[k]) || !isfinite(c->fluid_accel[k]))
       return fail(HLBM_EINVAL, "gravity / fluid_accel not finite");
@@ -143,6 +151,9 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
     y.eout = off; off += align_up((size_t)y.pool_cap * sizeof(float));
   }
   if (tables) {
+    for (int f = 0; f < NFAM; ++f) {
+      y.band[f] = off; off += align_up(BAND_BYTES);
+    }
     const long long side = (long long)floor(2.0 * (c->learned_max_circumradius + 0.5 * c->eps)) + 2;
     y.table_cap = side * side * side;
     y.tables = off; off += align_up((size_t)np * y.table_cap * sizeof(float));
@@ -183,6 +194,8 @@ struct hlbm_ctx {
   float *gpart, *gout, *epts, *eout;
   float4 *pool;
   float *tables;
+  float *band[NFAM];     // band grid of each family's shape at unit circumradius
+  int band_ok[NFAM];     // the grid holds the trained (or, for meshes, the current) shape
   int mode[NFAM];        // HLBM_INDICATOR_EXACT / LEARNED
   int has_params[NFAM];
   double aspect[NFAM];   // param[1] / param[0] of the trained shape, 0 = unknown
@@ -221,12 +234,14 @@ int refresh_tables(hlbm_ctx *c) {
   if (c->n == 0 || !c->tables) return HLBM_OK;
   // exact tables of mesh particles without a network
   if (c->mesh_particles && c->mode[2] != HLBM_INDICATOR_LEARNED)
-    HIP_TRY(launch_mesh_table(c->L, c->parts, c->n, c->tables, c->lay.table_cap, c->stream));
+    HIP_TRY(launch_mesh_table(c->L, c->parts, c->n, c->band_ok[2] ? c->band[2] : nullptr, c->tables,
+                              c->lay.table_cap, c->stream));
   if (!any_learned(c)) return HLBM_OK;
   LearnedNets nets;
   for (int f = 0; f < NFAM; ++f) {
     nets.theta[f] = c->theta[f];
     nets.packed[f] = c->packed[f];
+    nets.band[f] = c->band_ok[f] ? c->band[f] : nullptr;
   }
   HIP_TRY(launch_mlp_table(c->L, c->parts, c->n, nets, c->tables, c->lay.table_cap, c->stream));
   return HLBM_OK;
@@ -316,6 +331,8 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
     c->packed[f] = nullptr;
     c->mode[f] = HLBM_INDICATOR_EXACT;
     c->has_params[f] = 0;
+    c->band[f] = nullptr;
+    c->band_ok[f] = 0;
     c->aspect[f] = 0.0;
   }
   c->gpart = c->gout = c->epts = c->eout = c->tables = nullptr;
@@ -338,6 +355,7 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   }
   if (cfg->learned || cfg->max_mesh_triangles > 0) {
     c->tables = (float *)(c->base + lay.tables);
+    for (int f = 0; f < NFAM; ++f) c->band[f] = (float *)(c->base + lay.band[f]);
     c->L.tables = c->tables;
     c->L.table_cap = lay.table_cap;
   }
@@ -653,6 +671,10 @@ int hlbm_set_mesh(hlbm_ctx *ctx, const float *vertices, int32_t nv, const int32_
   ctx->L.mesh_nt = nt;
   ctx->mesh_rc = rc;
   ctx->mesh_rin = sqrt(rin2);
+  // band grid of the mesh at unit circumradius (scale 1 / rc)
+  HIP_TRY(band_grid(HLBM_MESH, 1.0 / rc, 0.0, ctx->mesh, nt, ctx->band[2], ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->band_ok[2] = 1;
   return HLBM_OK;
 }
 
@@ -1035,6 +1057,9 @@ int hlbm_train_indicator(hlbm_ctx *ctx, int32_t shape, const double *param, cons
     rep->iterations = o->iterations;
     rep->accepted = ok ? 1 : 0;
   }
+  // band grid of the trained shape (the same normalisation as the samples)
+  HIP_TRY(band_grid(shape, p0, p1, ctx->L.mesh, ctx->L.mesh_nt, ctx->band[f], s));
+  ctx->band_ok[f] = 1;
   // the mesh family's particles all have param[1] / param[0] = largest vertex radius
   ctx->aspect[f] = shape == HLBM_MESH ? ctx->mesh_rc : param[1] / param[0];
   ctx->mode[f] = ok ? HLBM_INDICATOR_LEARNED : HLBM_INDICATOR_EXACT;

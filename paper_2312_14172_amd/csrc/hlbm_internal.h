@@ -19,12 +19,14 @@ struct LearnedModes {
 struct LearnedNets {
   const float *theta[NFAM];
   const __bf16 *packed[NFAM];
+  const float *band[NFAM];  // band grid of the trained shape, or NULL
 };
 hipError_t launch_mark_learned(DevParticle *parts, int n, const LearnedModes &modes, hipStream_t s);
 hipError_t launch_mlp_table(const Lattice &L, const DevParticle *parts, int n, const LearnedNets &nets,
                             float *tables, long long cap, hipStream_t s);
-hipError_t launch_mesh_table(const Lattice &L, const DevParticle *parts, int n, float *tables, long long cap,
-                             hipStream_t s);
+// band: band grid of the mesh at unit circumradius, or NULL
+hipError_t launch_mesh_table(const Lattice &L, const DevParticle *parts, int n, const float *band, float *tables,
+                             long long cap, hipStream_t s);
 hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int cap, int *tcnt, int *tlist,
                       int *status, hipStream_t s);
 hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevParticle *parts, const int *order, int n,

@@ -22,6 +22,15 @@ constexpr int MLP_LANE_F4 = 28;              // float4 forward parameters per la
 constexpr int MLP_PACKED_BYTES = MLP_PACKED * 2 + 4 * MLP_LANE_F4 * 16;
 constexpr int MLP_MAX_BLOCKS = 512;          // workgroups of one gradient launch
 
+// Band grid of a family: the exact signed distance of its shape scaled to
+// unit circumradius, at the centres of BAND_G^3 voxels covering
+// [-BAND_HALF, BAND_HALF]^3 of the body frame (x fastest).  The table kernels
+// use it to settle the cells whose distance is certainly beyond +-eps/2.
+constexpr int BAND_G = 64;
+constexpr double BAND_HALF = 1.25;
+constexpr size_t BAND_BYTES = (size_t)BAND_G * BAND_G * BAND_G * sizeof(float);
+hipError_t band_grid(int shape, double p0, double p1, const float4 *mesh, int mesh_nt, float *out, hipStream_t s);
+
 hipError_t mlp_pack(const float *theta, __bf16 *packed, hipStream_t s);
 hipError_t mlp_eval(const float *theta, const __bf16 *packed, const float *pts, float *out, int n, hipStream_t s);
 hipError_t mlp_grad(const float *theta, const __bf16 *packed, const float4 *samples, int n, int nblocks,

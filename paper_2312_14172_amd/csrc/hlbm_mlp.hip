@@ -12,6 +12,8 @@
 // The weight matrices are stored pre-permuted in that order, so no data moves
 // between layers.  Weight-gradient products (contraction over samples) go
 // through LDS to transpose activations and errors.
+#include <algorithm>
+
 #include "hlbm_device.h"
 #include "hlbm_internal.h"
 #include "hlbm_mlp.h"
@@ -388,133 +390,261 @@ __global__ void k_sdf_samples(int shape, double p0, double p1, const float4 *mes
 }
 
 // ---------------------------------------------------------------------------
-// Learned distance table of each learned particle over its coupling box,
-// tables[pid * cap + lx + sx (ly + sy lz)]: the network is queried only on the
-// shell r_in - eps/2 <= |x - X| <= R_c + eps/2 (r_in the inscribed radius);
-// inside it the entry is R_c net(R^T (x - X) / R_c), below it -1e30 (certainly
-// inside, B = 1), above it +1e30 (certainly outside, B = 0) -- the same
-// early-outs the lattice kernel applies before reading the table.
-// grid = (ceil(cap / TAB_CHUNK), n), one wave per chunk of TAB_CHUNK cells: the
-// chunk's shell cells are compacted in LDS and evaluated in 16-cell tiles.
+// Band grid: the exact signed distance (FP64, stored in FP32) of the shape at
+// unit circumradius at every voxel centre; one thread per voxel.
 // ---------------------------------------------------------------------------
-constexpr int TAB_CHUNK = 128;
+__global__ void k_band_grid(int shape, double p0, double p1, const float4 *mesh, int mesh_nt,
+                            float *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= BAND_G * BAND_G * BAND_G) return;
+  const double h = 2.0 * BAND_HALF / BAND_G;
+  const double x = -BAND_HALF + (i % BAND_G + 0.5) * h;
+  const double y = -BAND_HALF + ((i / BAND_G) % BAND_G + 0.5) * h;
+  const double z = -BAND_HALF + (i / (BAND_G * BAND_G) + 0.5) * h;
+  out[i] = (float)(shape == 3 ? mesh_sdf<double>(mesh, mesh_nt, p0, x, y, z) : sdf_body<double>(shape, p0, p1, x, y, z));
+}
 
-__global__ __launch_bounds__(64) void k_mlp_table(Lattice L, const DevParticle *__restrict__ parts,
-                                                  LearnedNets nets, float *__restrict__ tables, long long cap) {
-  __shared__ int qidx[TAB_CHUNK];
-  __shared__ float qx[3][TAB_CHUNK];
-  const int pid = blockIdx.y;
-  const DevParticle &p = parts[pid];
-  if (p.learned != 1) return;
-  const int sx = p.hi[0] - p.lo[0] + 1, sy = p.hi[1] - p.lo[1] + 1, sz = p.hi[2] - p.lo[2] + 1;
-  const int total = sx * sy * sz;
-  const int base = blockIdx.x * TAB_CHUNK;
-  if (base >= total) return;
+// Settles a body-frame point b (in units of the circumradius rc) from the band
+// grid: +1 where its distance is certainly above eps/2 (B = 0, outside), -1
+// where certainly below -eps/2 (B = 1, inside), 0 where it must be evaluated.
+// The signed distance is 1-Lipschitz, so it differs from the value d(v) at the
+// voxel centre v by at most |b - v|; 1e-6 covers the FP32 rounding of d(v).
+// Points off the grid are always evaluated.
+__device__ inline int band_class(const float *__restrict__ band, double b0, double b1, double b2, double rc,
+                                 double half_eps) {
+  if (!band) return 0;
+  const double ih = BAND_G / (2.0 * BAND_HALF), h = 2.0 * BAND_HALF / BAND_G;
+  const double u0 = (b0 + BAND_HALF) * ih, u1 = (b1 + BAND_HALF) * ih, u2 = (b2 + BAND_HALF) * ih;
+  if (!(u0 >= 0.0 && u0 < BAND_G && u1 >= 0.0 && u1 < BAND_G && u2 >= 0.0 && u2 < BAND_G)) return 0;
+  const int i0 = (int)u0, i1 = (int)u1, i2 = (int)u2;
+  const double v0 = b0 - (-BAND_HALF + (i0 + 0.5) * h), v1 = b1 - (-BAND_HALF + (i1 + 0.5) * h),
+               v2 = b2 - (-BAND_HALF + (i2 + 0.5) * h);
+  const double r2 = v0 * v0 + v1 * v1 + v2 * v2;
+  const double d = (double)band[i0 + BAND_G * (i1 + BAND_G * i2)];
+  const double e = half_eps / rc + 1e-6;
+  // d - |b - v| > e  and  d + |b - v| < -e, without the square root
+  const double out = d - e, in = -d - e;
+  if (out > 0.0 && out * out > r2) return 1;
+  if (in > 0.0 && in * in > r2) return -1;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Distance tables over each particle's coupling box,
+// tables[pid * cap + lx + sx (ly + sy lz)], for the particles read through a
+// table (learned shapes, and mesh shapes without a network).  A cell is
+// settled without evaluating the distance where it is certainly farther than
+// eps/2 from the surface: outside R_c + eps/2 or, by the band grid, outside
+// by more than eps/2 (entry +1e30, B = 0); inside r_in - eps/2 (r_in the
+// inscribed radius) or, by the band grid, inside by more than eps/2 (entry
+// -1e30, B = 1) -- the values the lattice kernel gives the cells it settles
+// before reading a table.  The other cells are evaluated: by the network,
+// R_c net(R^T (x - X) / R_c), or by the exact mesh distance.
+//
+// One workgroup of 256 threads per (chunk, particle); a particle's box is cut
+// into nchunk contiguous chunks (more chunks when there are few particles, so
+// that the launch fills the chip).  A chunk is classified 256 cells at a time,
+// the cells to evaluate are appended to an LDS queue, and every 256 queued
+// cells are evaluated by all threads at once (the network on full 16-cell
+// tiles, the mesh distance on full wavefronts); the remainder at the end.
+// Queue entries are box cell indices; the body-frame point is formed again
+// from them in FP64.
+// ---------------------------------------------------------------------------
+constexpr int TAB_QUEUE = 512;
+
+struct TableBox {
+  int sx, sy, total;
+  float isx, isxy;       // 1 / sx, 1 / (sx sy)
+  double lo2, hi2, inv;  // early-out radii (as squares below), 1 / R_c
+};
+
+__device__ inline TableBox table_box(const Lattice &L, const DevParticle &p, double rin) {
+  TableBox b;
+  b.sx = p.hi[0] - p.lo[0] + 1;
+  b.sy = p.hi[1] - p.lo[1] + 1;
+  b.total = b.sx * b.sy * (p.hi[2] - p.lo[2] + 1);
+  b.isx = 1.0f / (float)b.sx;
+  b.isxy = 1.0f / (float)(b.sx * b.sy);
+  b.lo2 = rin - 0.5 * L.eps;
+  b.hi2 = p.rc + 0.5 * L.eps;
+  b.inv = 1.0 / p.rc;
+  return b;
+}
+
+// q = floor(i / m) for 0 <= i, 0 < m, from the FP32 product (i + 1/2) im
+// (im = 1 / m in FP32) corrected by one step either way: the product is off
+// by less than one while i < 2^22.
+__device__ inline int div_fix(int i, int m, float im) {
+  int q = (int)(((float)i + 0.5f) * im);
+  const int r = i - q * m;
+  q += r < 0 ? -1 : (r >= m ? 1 : 0);
+  return q;
+}
+
+// Offset of box cell idx from the centre (box cells are unwrapped, so no
+// minimum image is needed) and its body-frame image R^T d.
+__device__ inline void table_point(const DevParticle &p, const TableBox &tb, int idx, double *d, double *bf) {
+  const int zy = div_fix(idx, tb.sx, tb.isx), z = div_fix(idx, tb.sx * tb.sy, tb.isxy);
+  d[0] = (p.lo[0] + (idx - zy * tb.sx) + 0.5) - p.X[0];
+  d[1] = (p.lo[1] + (zy - z * tb.sy) + 0.5) - p.X[1];
+  d[2] = (p.lo[2] + z + 0.5) - p.X[2];
+  const double *R = p.R;
+  bf[0] = R[0] * d[0] + R[3] * d[1] + R[6] * d[2];
+  bf[1] = R[1] * d[0] + R[4] * d[1] + R[7] * d[2];
+  bf[2] = R[2] * d[0] + R[5] * d[1] + R[8] * d[2];
+}
+
+// Classify the box cells [begin, end) and drain the queue through
+// eval(queue, count): called by all 256 threads with count = 256 as the queue
+// fills, then once with the rest (possibly 0).
+template <class Eval>
+__device__ inline void table_cells(const Lattice &L, const DevParticle &p, const TableBox &tb, int begin, int end,
+                                   const float *__restrict__ band, float *__restrict__ tab, int *queue, int *wcnt,
+                                   Eval eval) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  int queued = 0;  // uniform
+  for (int base = begin; base < end; base += 256) {
+    const int idx = base + t;
+    bool q = false;
+    if (idx < end) {
+      double d[3], bf[3];
+      table_point(p, tb, idx, d, bf);
+      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      int cls;
+      if (r2 > tb.hi2 * tb.hi2) cls = 1;
+      else if (tb.lo2 > 0.0 && r2 < tb.lo2 * tb.lo2) cls = -1;
+      else cls = band_class(band, bf[0] * tb.inv, bf[1] * tb.inv, bf[2] * tb.inv, p.rc, 0.5 * L.eps);
+      if (cls != 0) tab[idx] = cls > 0 ? 1e30f : -1e30f;
+      else q = true;
+    }
+    const unsigned long long mask = __ballot(q);
+    if (l == 0) wcnt[w] = __popcll(mask);
+    __syncthreads();
+    int off = queued, added = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      off += k < w ? wcnt[k] : 0;
+      added += wcnt[k];
+    }
+    if (q) queue[off + __popcll(mask & ((1ull << l) - 1ull))] = idx;
+    queued += added;
+    __syncthreads();
+    if (queued >= 256) {
+      eval(queue, 256);
+      const int rest = queued - 256;
+      const int keep = t < rest ? queue[256 + t] : 0;
+      __syncthreads();
+      if (t < rest) queue[t] = keep;
+      queued = rest;
+      __syncthreads();
+    }
+  }
+  eval(queue, queued);
+}
+
+// Chunk blockIdx.x of nchunk of the box: [begin, end), whole 256-cell rounds.
+__device__ inline void table_chunk(const TableBox &tb, int nchunk, int &begin, int &end) {
+  const int per = ((tb.total + nchunk - 1) / nchunk + 255) / 256 * 256;
+  begin = min(tb.total, (int)blockIdx.x * per);
+  end = min(tb.total, begin + per);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_table(Lattice L, const DevParticle *__restrict__ parts,
+                                                   LearnedNets nets, int nchunk, float *__restrict__ tables,
+                                                   long long cap) {
+  __shared__ int queue[TAB_QUEUE];
+  __shared__ int wcnt[4];
+  const DevParticle &p = parts[blockIdx.y];
+  if (p.learned != 1) return;  // uniform per workgroup
   const int fam = min(max(p.shape - 1, 0), NFAM - 1);  // learned particles are shapes 1..3
   const MlpArgs A = mlp_args(nets.theta[fam], nets.packed[fam]);
-  const int l = threadIdx.x, g = l >> 4, li = l & 15;
-  const double rc = p.rc, inv = 1.0 / rc;
   const double rin = p.shape == 2 ? fmin(p.prm[0], p.prm[1]) : (p.shape == 3 ? p.prm[2] : p.prm[0]);
-  const double lo2 = rin - 0.5 * L.eps, hi2 = rc + 0.5 * L.eps;
-  float *tab = tables + (size_t)pid * cap;
-  // classify; compact the shell cells (in cell order)
-  int nq = 0;  // wave-uniform
-  for (int k = 0; k < TAB_CHUNK / 64; ++k) {
-    const int idx = base + k * 64 + l;
-    bool shell = false;
-    float b0 = 0.f, b1 = 0.f, b2 = 0.f;
-    if (idx < total) {
-      // box cells are unwrapped, so x - X needs no minimum image
-      const double d0 = (p.lo[0] + idx % sx + 0.5) - p.X[0];
-      const double d1 = (p.lo[1] + (idx / sx) % sy + 0.5) - p.X[1];
-      const double d2 = (p.lo[2] + idx / (sx * sy) + 0.5) - p.X[2];
-      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-      if (r2 > hi2 * hi2) {
-        tab[idx] = 1e30f;
-      } else if (lo2 > 0.0 && r2 < lo2 * lo2) {
-        tab[idx] = -1e30f;
-      } else {
-        shell = true;
-        const double *R = p.R;
-        b0 = (float)((R[0] * d0 + R[3] * d1 + R[6] * d2) * inv);
-        b1 = (float)((R[1] * d0 + R[4] * d1 + R[7] * d2) * inv);
-        b2 = (float)((R[2] * d0 + R[5] * d1 + R[8] * d2) * inv);
-      }
-    }
-    const unsigned long long mask = __ballot(shell);
-    if (shell) {
-      const int slot = nq + __popcll(mask & ((1ull << l) - 1ull));
-      qidx[slot] = idx;
-      qx[0][slot] = b0;
-      qx[1][slot] = b1;
-      qx[2][slot] = b2;
-    }
-    nq += __popcll(mask);
-  }
-  __syncthreads();
-  // evaluate 64 shell cells per pass as four 16-cell tiles
-  for (int t0 = 0; t0 < nq; t0 += 64) {
+  const TableBox tb = table_box(L, p, rin);
+  int begin, end;
+  table_chunk(tb, nchunk, begin, end);
+  if (begin >= end) return;  // uniform per workgroup
+  float *tab = tables + (size_t)blockIdx.y * cap;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, li = l & 15;
+  // each wavefront evaluates its 64 queue entries as four 16-cell tiles
+  table_cells(L, p, tb, begin, end, nets.band[fam], tab, queue, wcnt, [&](const int *qu, int count) {
     for (int q = 0; q < 4; ++q) {
+      const int k = w * 64 + q * 16 + li;
+      if (w * 64 + q * 16 >= count) break;  // uniform per wavefront
       // the per-lane parameters are re-read (L1) for every tile instead of
       // being hoisted out of the loop: that would hold ~110 more registers and
       // halve the waves per SIMD that hide the MFMA and SiLU latencies
       __asm__ volatile("" ::: "memory");
-      const int k = t0 + q * 16 + li;
-      const bool ok = k < nq;
-      const float x0 = ok ? qx[0][k] : 0.f, x1 = ok ? qx[1][k] : 0.f, x2 = ok ? qx[2][k] : 0.f;
+      const bool ok = k < count;
+      const int idx = ok ? qu[k] : 0;
+      float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+      if (ok) {
+        double d[3], bf[3];
+        table_point(p, tb, idx, d, bf);
+        x0 = (float)(bf[0] * tb.inv);
+        x1 = (float)(bf[1] * tb.inv);
+        x2 = (float)(bf[2] * tb.inv);
+      }
       float z1[16], z2[16], z3[16], y;
       mlp_forward_tile(A, x0, x1, x2, z1, z2, z3, y);
-      if (ok && g == 0) tab[qidx[k]] = (float)(y * rc);
+      if (ok && g == 0) tab[idx] = (float)(y * p.rc);
     }
-  }
+  });
 }
 
 // Exact distance table of the mesh particles without a network (learned ==
-// 2): same layout, shell and early-outs as k_mlp_table, with the mesh's signed
-// distance (FP64, stored in FP32) on the shell.  One thread per coupling-box
-// cell; grid = (ceil(cap / 256), n).
+// 2): the mesh's signed distance (FP64, stored in FP32), one queued cell per
+// thread.
 __global__ __launch_bounds__(256) void k_mesh_table(Lattice L, const DevParticle *__restrict__ parts,
+                                                   const float *__restrict__ band, int nchunk,
                                                    float *__restrict__ tables, long long cap) {
-  const int pid = blockIdx.y;
-  const DevParticle &p = parts[pid];
-  if (p.learned != 2) return;
-  const int sx = p.hi[0] - p.lo[0] + 1, sy = p.hi[1] - p.lo[1] + 1, sz = p.hi[2] - p.lo[2] + 1;
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= sx * sy * sz) return;
-  const double d0 = (p.lo[0] + idx % sx + 0.5) - p.X[0];
-  const double d1 = (p.lo[1] + (idx / sx) % sy + 0.5) - p.X[1];
-  const double d2 = (p.lo[2] + idx / (sx * sy) + 0.5) - p.X[2];
-  const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-  const double lo2 = p.prm[2] - 0.5 * L.eps, hi2 = p.rc + 0.5 * L.eps;
-  float *tab = tables + (size_t)pid * cap;
-  if (r2 > hi2 * hi2) {
-    tab[idx] = 1e30f;
-  } else if (lo2 > 0.0 && r2 < lo2 * lo2) {
-    tab[idx] = -1e30f;
-  } else {
-    const double *R = p.R;
-    const double b0 = R[0] * d0 + R[3] * d1 + R[6] * d2;
-    const double b1 = R[1] * d0 + R[4] * d1 + R[7] * d2;
-    const double b2 = R[2] * d0 + R[5] * d1 + R[8] * d2;
-    tab[idx] = (float)mesh_sdf<double>(L.mesh, L.mesh_nt, p.prm[0], b0, b1, b2);
-  }
+  __shared__ int queue[TAB_QUEUE];
+  __shared__ int wcnt[4];
+  const DevParticle &p = parts[blockIdx.y];
+  if (p.learned != 2) return;  // uniform per workgroup
+  const TableBox tb = table_box(L, p, p.prm[2]);
+  int begin, end;
+  table_chunk(tb, nchunk, begin, end);
+  if (begin >= end) return;  // uniform per workgroup
+  float *tab = tables + (size_t)blockIdx.y * cap;
+  table_cells(L, p, tb, begin, end, band, tab, queue, wcnt, [&](const int *qu, int count) {
+    if ((int)threadIdx.x < count) {
+      const int idx = qu[threadIdx.x];
+      double d[3], bf[3];
+      table_point(p, tb, idx, d, bf);
+      tab[idx] = (float)mesh_sdf<double>(L.mesh, L.mesh_nt, p.prm[0], bf[0], bf[1], bf[2]);
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_mesh_table(const Lattice &L, const DevParticle *parts, int n, float *tables, long long cap,
-                             hipStream_t s) {
+// Chunks per particle box of the table kernels: about 2048 workgroups in all,
+// at most one per 1024 cells of the largest box.
+static int table_chunks(int n, long long cap) {
+  const long long k = std::min<long long>((2048 + n - 1) / n, (cap + 1023) / 1024);
+  return (int)std::max<long long>(1, k);
+}
+
+hipError_t launch_mesh_table(const Lattice &L, const DevParticle *parts, int n, const float *band, float *tables,
+                             long long cap, hipStream_t s) {
   if (n <= 0 || !tables || L.mesh_nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mesh_table, dim3((unsigned)((cap + 255) / 256), n), dim3(256), 0, s, L, parts, tables, cap);
+  hipLaunchKernelGGL(k_mesh_table, dim3(table_chunks(n, cap), n), dim3(256), 0, s, L, parts, band,
+                     table_chunks(n, cap), tables, cap);
+  return hipGetLastError();
+}
+
+hipError_t band_grid(int shape, double p0, double p1, const float4 *mesh, int mesh_nt, float *out, hipStream_t s) {
+  constexpr int nv = BAND_G * BAND_G * BAND_G;
+  hipLaunchKernelGGL(k_band_grid, dim3((nv + 255) / 256), dim3(256), 0, s, shape, p0, p1, mesh, mesh_nt, out);
   return hipGetLastError();
 }
 
 hipError_t launch_mlp_table(const Lattice &L, const DevParticle *parts, int n, const LearnedNets &nets,
                             float *tables, long long cap, hipStream_t s) {
   if (n <= 0 || !tables) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_table, dim3((unsigned)((cap + TAB_CHUNK - 1) / TAB_CHUNK), n), dim3(64), 0, s, L, parts,
-                     nets, tables, cap);
+  hipLaunchKernelGGL(k_mlp_table, dim3(table_chunks(n, cap), n), dim3(256), 0, s, L, parts, nets,
+                     table_chunks(n, cap), tables, cap);
   return hipGetLastError();
 }
 

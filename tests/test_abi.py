@@ -60,6 +60,8 @@ def test_workspace_size_counts_both_population_buffers():
     (dict(n=(8, 8, 8), bc=(0, 2, 0)), -1),
     (dict(n=(8, 8, 8), precision=7), -1),
     (dict(n=(8, 8, 8), max_particles=-1), -1),
+    # distance tables of (2 (27 + 100) + 2)^3 cells per particle
+    (dict(n=(8, 8, 8), max_particles=1, learned_max_circumradius=27.0, max_mesh_triangles=4, eps=200.0), -6),
 ])
 def test_invalid_configurations_are_rejected(kw, code):
     rc, _ = _size(**kw)

@@ -168,3 +168,47 @@ def test_learned_coupling_against_exact(H):
     assert dB.mean() <= 0.05
     assert abs(le["B0"].sum() / ex["B0"].sum() - 1) <= 5e-3
     assert le["ms"] > 0 and ex["ms"] > 0
+
+
+@pytest.mark.parametrize("shape", [W.ROUNDED_CUBE, W.SPHEROID, W.MESH])
+def test_band_grid_settles_only_far_cells(H, oracle_mod, shape):
+    """The band grid of a trained shape settles the table cells whose distance
+    is certainly beyond +-eps/2 and leaves the others to the network.  With a
+    network that answers d = 0 everywhere, every cell the network decides has
+    B = 1/2 exactly, so the settled cells can be told apart: each must carry
+    the exact indicator of the FP64 oracle (0 or 1), every cell of the exact
+    band 0 < B < 1 must have been left to the network, and the cells left to
+    it may number at most four times the band (without the grid the whole
+    shell between r_in - eps/2 and R_c + eps/2 is queried)."""
+    n, bc = (48, 36, 32), (0, 0, 1)
+    rng = np.random.default_rng(3 + shape)
+    prm = W.equal_volume_params(shape, 6.0)
+    # the particle straddles the periodic x face
+    parts = np.array([W.make_particle(shape, prm, (1.3, 17.6, 15.2), quat=W.shoemake_quaternion(rng))])
+    kw = {}
+    if shape == W.MESH:
+        v, t = W.MESH_UNIT
+        kw["max_mesh_triangles"] = len(t)
+    sim = _sim(H, n, bc, "fp64", max_particles=1, samples=8192, **kw)
+    if shape == W.MESH:
+        sim.set_mesh(v, t)
+    _log(f"gpu: band grid of shape {shape}, network d = 0")
+    sim.mlp_set_params(shape, W.mlp_init_params(7 + shape))
+    sim.train_indicator(shape, prm[:2], samples=4096, holdout=64, iterations=1, batch=1024,
+                        gate_rms=1e-9, gate_max=1e-9)
+    sim.mlp_set_params(shape, np.zeros(H.MLP_NPARAM, dtype=np.float32))
+    sim.set_indicator(shape, H.INDICATOR_LEARNED)
+    sim.set_particles(parts)
+    B = sim.get_fields(H.FIELD_SOLID)["B"]
+    sim.close()
+    if shape == W.MESH:
+        oracle_mod.Oracle.set_mesh(v, t)
+    orc = oracle_mod.Oracle(n, bc, 0.8)
+    Bo, _ = orc.coupling(orc.to_parts(parts))
+    queried = np.abs(B - 0.5) <= 1e-12
+    band = (Bo > 0) & (Bo < 1)
+    _log(f"  queried {int(queried.sum())}  exact band {int(band.sum())}  "
+         f"settled {int((~queried).sum())} (B = 1: {int((B == 1).sum())})")
+    np.testing.assert_array_equal(B[~queried], Bo[~queried])
+    assert queried[band].all()
+    assert band.sum() > 100 and queried.sum() <= 4 * band.sum()

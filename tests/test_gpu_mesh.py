@@ -96,11 +96,11 @@ def test_learned_mesh_indicator_gains_over_exact(H):
     it.  Checked: the network passes its gate, porosity on smoothed-boundary
     cells (mean |dB| <= 0.08: the facet edges make this distance less smooth
     than the closed-form shapes') and solid volume agree, time-averaged forces
-    agree within 1 % RMS over particles, and the step is at least 5x faster
-    with the network (the exact distance costs 320 triangle distances and
-    solid angles per shell cell in FP64, the network 16.9 kFLOP of BF16 matrix
-    products).  Measured: porosity L1 0.052, volume +0.2 %, force 0.34 %,
-    1.61 vs 0.118 ms per step (13.6x)."""
+    agree within 1 % RMS over particles, and the step is at least 3x faster
+    with the network (on every cell the band grid leaves open, the exact
+    distance costs 320 triangle distances and solid angles in FP64, the
+    network 16.9 kFLOP of BF16 matrix products).  Measured: porosity L1
+    0.053, volume +0.2 %, force 0.34 %, 0.550 vs 0.115 ms per step (4.8x)."""
     import torch
     n, bc = (128, 128, 128), (0, 0, 1)
     v, t = W.MESH_UNIT
@@ -144,7 +144,7 @@ def test_learned_mesh_indicator_gains_over_exact(H):
     assert dB.mean() <= 0.08
     assert abs(le["B0"].sum() / ex["B0"].sum() - 1) <= 5e-3
     assert ferr <= 0.01
-    assert gain >= 5.0
+    assert gain >= 3.0
 
 
 def test_mesh_validation(H):
