@@ -13,12 +13,13 @@ What is checked:
     sphere repulsion of hlbm_set_contact (range 2 cells, stiffness 8
     submerged weights) brings it within [0.95, 1.15] of it (measured +51 % and
     +4 %), the effect the paper expects of a contact model;
-  * resolution: N = 12 and N = 18 agree at phi = 0.1 within 2 % (the paper's
-    grid study finds errors below 2 % from N = 12 on) plus twice the
-    statistical error of the difference.  A single run is one realisation of
-    a chaotic suspension: a change in the last bit of the forces (another
-    floating-point contraction order) moved the N = 18 mean by 1.9 %, so the
-    time-average's standard error (batch means) is part of the bound."""
+  * resolution: at phi = 0.1 the means over two realisations (seeds 7 and 8)
+    at N = 12 and at N = 18 agree within 2 %, the paper's grid-study bound
+    (errors below 2 % from N = 12 on).  A single run is one realisation of a
+    chaotic suspension (a change in the last bit of the forces moved an
+    N = 18 mean by 1.9 %); the two-seed means halve that spread.  Measured:
+    0.8092 / 0.8134 for seed 8 at N = 12 / 18, batch-mean standard errors
+    0.004-0.006."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -37,11 +38,11 @@ def S():
     return settling
 
 
-def _run(S, phi, N, contact=None):
-    key = (phi, N, contact)
+def _run(S, phi, N, contact=None, seed=7):
+    key = (phi, N, contact, seed)
     if key not in _RUNS:
-        print(f"settling: phi {phi}, N {N}, contact {contact}", flush=True)
-        _RUNS[key] = S.run_periodic(phi, N=N, seed=7, gap=1.0 if phi < 0.25 else 0.2, contact=contact)
+        print(f"settling: phi {phi}, N {N}, contact {contact}, seed {seed}", flush=True)
+        _RUNS[key] = S.run_periodic(phi, N=N, seed=seed, gap=1.0 if phi < 0.25 else 0.2, contact=contact)
         r = _RUNS[key]
         print(f"  u_bar/u* {r['ratio']:.4f} +- {r['ratio_se']:.4f}  RZ {r['rz']:.4f}  GAD {r['gad']:.4f}  BM {r['bm']:.4f}  "
               f"flux {r['mean_flux']:.2e}  {r['seconds']:.1f} s", flush=True)
@@ -67,9 +68,11 @@ def test_contact_closes_the_gap_at_high_phi(S):
 
 
 def test_settling_resolution_independence(S):
-    a, b = _run(S, 0.1, 12), _run(S, 0.1, 18)
-    # standard errors measured: 0.0072 (N = 12) and 0.0037 (N = 18), so the
-    # bound is about 4 %; the means differ by 0.9 %
-    noise = 2.0 * (a["ratio_se"] ** 2 + b["ratio_se"] ** 2) ** 0.5
-    assert noise == noise and b["samples"] > 100
-    assert abs(a["ratio"] - b["ratio"]) <= 0.02 * b["ratio"] + noise
+    a = [_run(S, 0.1, 12, seed=s) for s in (7, 8)]
+    b = [_run(S, 0.1, 18, seed=s) for s in (7, 8)]
+    for r in a + b:
+        assert r["samples"] > 100 and abs(r["mean_flux"]) <= 0.01 * r["u_star"]
+    ma = sum(r["ratio"] for r in a) / 2
+    mb = sum(r["ratio"] for r in b) / 2
+    print(f"  two-seed means: N = 12 {ma:.4f}, N = 18 {mb:.4f}, difference {abs(ma - mb) / mb:.2%}", flush=True)
+    assert abs(ma - mb) <= 0.02 * mb
