@@ -16,7 +16,7 @@
  *     is inside the particle, force and torque (Sec. 3.2, MEA, force and
  *     torque equations);
  *   - Newton-Euler equations with gravity and buoyancy (Sec. 2.2, Sec. 5.1),
- *     and optionally a sphere contact force (hlbm_set_contact);
+ *     and optionally a contact force and torque (hlbm_set_contact);
  *   - in the order of the paper's time-step algorithm (Sec. 4.2, Algorithm 1); its
  *     communication and assignment steps have nothing to do on one GPU.
  *
@@ -198,20 +198,28 @@ int hlbm_set_mesh(hlbm_ctx *ctx, const float *vertices, int32_t nv, const int32_
  * with HLBM_EINVAL and leave the acceleration unchanged. */
 int hlbm_set_fluid_accel(hlbm_ctx *ctx, const double accel[3]);
 
-/* Sphere contact, off by default.  Sec. 2.2 lets contact forces enter the
+/* Particle contact, off by default.  Sec. 2.2 lets contact forces enter the
  * particles' equations of motion next to the hydrodynamic ones; Sec. 3.2
- * leaves the cited contact model out on purpose, and Sec. 5.3
- * names the missing contact model as the likely cause of the overestimated
- * settling velocities at high volume fractions, without giving a model.
- * This is the short-range repulsion of Glowinski et al. (J. Comput. Phys.
- * 169, 2001): spheres whose centres are closer than R_p + R_q + range repel
- * along the line of centres with stiffness * ((R_p + R_q + range - d) /
- * range)^2 (minimum image on periodic axes), and a wall pushes a sphere whose
- * centre is at distance h with wall_stiffness * ((2 R + range - 2 h) /
- * range)^2 (its mirror image).  Only spheres take part; the force acts on the
- * state of the step's momentum exchange and is added to the hydrodynamic
- * force in the equations of motion (hlbm_get_forces still reports the
- * hydrodynamic force alone).  All n^2 pairs are tested every step.
+ * leaves the cited contact model (one for arbitrary convex shapes) out on
+ * purpose, and Sec. 5.3 names the missing contact model as the likely cause
+ * of the overestimated settling velocities at high volume fractions, without
+ * giving a model.  Spheres: the short-range repulsion of Glowinski et al.
+ * (J. Comput. Phys. 169, 2001): spheres whose centres are closer than
+ * R_p + R_q + range repel along the line of centres with stiffness *
+ * ((R_p + R_q + range - d) / range)^2 (minimum image on periodic axes), and a
+ * wall pushes a sphere whose centre is at distance h with wall_stiffness *
+ * ((2 R + range - 2 h) / range)^2 (its mirror image).  Pairs with a
+ * non-spherical particle (and such particles at walls): the same repulsion
+ * written as a volume law, stiffness * V / (pi R_eff range^2) with V the
+ * overlap of the two bodies grown by range / 2, evaluated on 1024 surface
+ * nodes of each body against the partner's signed distance and applied at
+ * the nodes along the partner's normal, so that it also exerts a torque
+ * (R_eff = R_p R_q / (R_p + R_q) from volume-equivalent radii; R_p / 2 and
+ * the mirror image at a wall); for two spheres it reduces to the law above
+ * to leading order in the penetration.  The force and torque act on the
+ * state of the step's momentum exchange and are added to the hydrodynamic
+ * ones in the equations of motion (hlbm_get_forces still reports the
+ * hydrodynamic force and torque alone).  All n^2 pairs are tested every step.
  * Stream-ordered like hlbm_set_fluid_accel; range = 0 or both stiffnesses 0
  * turn it off.  HLBM_EINVAL for negative or non-finite values. */
 int hlbm_set_contact(hlbm_ctx *ctx, double range, double stiffness, double wall_stiffness);

@@ -560,22 +560,53 @@ void orc_apply_eom(const ocfg *cfg, int np, opart *P, const double *F, const dou
 }
 
 /* ---------------------------------------------------------------------------
- * Contact between spheres (an addition: the paper runs without a contact
- * model and names one only by citation, Sec. 2.2, Sec. 3.2 and Sec. 5.3).
- * reading: the short-range repulsion of Glowinski, Pan, Hesla, Joseph and
- * Periaux (J. Comput. Phys. 169, 2001).  Two spheres whose centres are closer
- * than R_p + R_q + zeta repel along the line of centres with
+ * Contact (an addition: the paper runs without a contact model and names one
+ * only by citation, Sec. 2.2, Sec. 3.2 and Sec. 5.3).
+ *
+ * Sphere pairs -- reading: the short-range repulsion of Glowinski, Pan,
+ * Hesla, Joseph and Periaux (J. Comput. Phys. 169, 2001).  Two spheres whose
+ * centres are closer than R_p + R_q + zeta repel along the line of centres
+ * with
  *     F_pq = k ((R_p + R_q + zeta - d) / zeta)^2 (X_p - X_q) / d,
  * and a wall acts on a sphere like its mirror image (centre distance
  * d' = 2 h, h the distance of the centre from the wall):
  *     F_pw = k_w ((2 R_p + zeta - d') / zeta)^2, directed away from the wall.
- * Only sphere pairs take part; separations are minimum images on periodic
- * axes; the state is that of time t (the one the momentum exchange reads), and
- * the force is added to the hydrodynamic force in the equations of motion.
- * Sums run over q = 0, 1, ..., np-1, then the walls axis by axis (lower wall
+ *
+ * Pairs with a non-spherical particle, and such particles at walls -- reading:
+ * the same repulsion written as a volume law and evaluated on surface nodes
+ * against the partner's signed distance (nodes probing a level set, as in the
+ * level-set discrete element method of Kawamoto, Ando, Viggiani and Andrade,
+ * J. Mech. Phys. Solids 91, 2016).  Grow both bodies by zeta/2; the volume of
+ * their overlap is V = 1/2 (int_{dP} delta_q dA + int_{dQ} delta_p dA), with
+ * delta_q(s) = max(0, zeta - d_q(s)) the depth of a surface point s of P in
+ * the grown Q, and the force on P is
+ *     F_P = k V / (pi R_eff zeta^2),  R_eff = R_P R_Q / (R_P + R_Q),
+ * R the volume-equivalent radius, spread over the surface points along the
+ * partner's outward normal grad d:
+ *     F_P = K [ sum_{s in P} 1/2 a_s delta_q(s) grad d_q(s)
+ *             - sum_{s in Q} 1/2 a_s delta_p(s) grad d_p(s) ],
+ *     T_P = K [ sum_{s in P} (s - X_P) x (...) - sum_{s in Q} (s - X_P) x (...) ],
+ * K = k / (pi R_eff zeta^2).  For two spheres V = pi R_eff h^2 to leading
+ * order in the penetration h = R_p + R_q + zeta - d, so the law reduces to the
+ * sphere law above.  A wall acts like the mirror image: delta_w(s) =
+ * max(0, zeta - 2 h_s) with h_s the distance of s from the wall, V =
+ * sum_s a_s delta_w(s), R_eff = R_P / 2, K_w = k_w / (pi (R_P / 2) zeta^2),
+ * along the wall normal (for a sphere again the sphere law).
+ * Surface nodes: M directions of a Fibonacci lattice on the unit sphere
+ * (z_m = 1 - (2 m + 1) / M, azimuth m times the golden angle pi (3 - sqrt 5)),
+ * the surface point on the ray from the centre by bisection of the signed
+ * distance on [0, R_circ] (the bodies are star-shaped about their centre),
+ * outward normal n the normalised gradient of the signed distance (central
+ * differences, step 1e-5), area weight a = (4 pi / M) t^2 / (u . n) (the
+ * surface element of a star-shaped body per solid angle).
+ * Separations are minimum images on periodic axes; the state is that of time
+ * t (the one the momentum exchange reads); force and torque are added to the
+ * hydrodynamic ones in the equations of motion.  Sums run over q = 0, 1, ...,
+ * np-1 (nodes of P, then nodes of Q), then the walls axis by axis (lower wall
  * first).
  * ------------------------------------------------------------------------- */
 static double g_contact_range = 0.0, g_contact_k = 0.0, g_contact_kw = 0.0;
+static int g_contact_nodes = 1024;
 
 void orc_set_contact(double range, double k, double kw) {
     g_contact_range = range;
@@ -583,40 +614,170 @@ void orc_set_contact(double range, double k, double kw) {
     g_contact_kw = kw;
 }
 
+/* number of surface nodes per particle (1024 unless a test changes it) */
+void orc_set_contact_nodes(int M) { g_contact_nodes = M > 0 ? M : 1024; }
+
+static double inscribed_radius(const opart *P) {
+    switch (P->shape) {
+    case SH_SPHERE: return P->prm[0];
+    case SH_ROUNDED_CUBE: return P->prm[0];
+    case SH_SPHEROID: return fmin(P->prm[0], P->prm[1]);
+    case SH_MESH: return P->prm[2];
+    default: return 0.0;
+    }
+}
+
+static double vol_radius(const opart *P) { return cbrt(3.0 * P->V / (4.0 * M_PI)); }
+
+/* normalised central-difference gradient of the body-frame signed distance */
+static void sdf_normal(const opart *P, const double *b, double *g) {
+    const double h = 1e-5;
+    double nn = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double bp[3] = {b[0], b[1], b[2]}, bm[3] = {b[0], b[1], b[2]};
+        bp[k] += h;
+        bm[k] -= h;
+        g[k] = (orc_sdf(P->shape, P->prm, bp) - orc_sdf(P->shape, P->prm, bm)) / (2.0 * h);
+        nn += g[k] * g[k];
+    }
+    nn = sqrt(nn);
+    for (int k = 0; k < 3; ++k) g[k] /= nn;
+}
+
+/* Surface node m of M: body-frame position b, body-frame outward normal n,
+ * area weight a. */
+static void surface_node(const opart *P, int m, int M, double *b, double *n, double *a) {
+    const double z = 1.0 - (2.0 * m + 1.0) / M, r = sqrt(fmax(0.0, 1.0 - z * z));
+    const double ph = m * (M_PI * (3.0 - sqrt(5.0)));
+    const double u[3] = {r * cos(ph), r * sin(ph), z};
+    double lo = 0.0, hi = orc_circumradius(P->shape, P->prm);
+    for (int it = 0; it < 60; ++it) {
+        const double t = 0.5 * (lo + hi), p[3] = {t * u[0], t * u[1], t * u[2]};
+        if (orc_sdf(P->shape, P->prm, p) < 0.0) lo = t; else hi = t;
+    }
+    const double t = 0.5 * (lo + hi);
+    for (int k = 0; k < 3; ++k) b[k] = t * u[k];
+    sdf_normal(P, b, n);
+    *a = (4.0 * M_PI / M) * t * t / (u[0] * n[0] + u[1] * n[1] + u[2] * n[2]);
+}
+
+static void rot_apply(double R[3][3], const double *v, double *o) {
+    for (int k = 0; k < 3; ++k) o[k] = R[k][0] * v[0] + R[k][1] * v[1] + R[k][2] * v[2];
+}
+static void rot_apply_t(double R[3][3], const double *v, double *o) {
+    for (int k = 0; k < 3; ++k) o[k] = R[0][k] * v[0] + R[1][k] * v[1] + R[2][k] * v[2];
+}
+static void add_cross(const double *r, const double *f, double s, double *T) {
+    T[0] += s * (r[1] * f[2] - r[2] * f[1]);
+    T[1] += s * (r[2] * f[0] - r[0] * f[2]);
+    T[2] += s * (r[0] * f[1] - r[1] * f[0]);
+}
+
+/* Node sums of one side: the nodes of A (centre at the origin) probing the
+ * grown B (centre at e); adds sign * K/2 a delta grad d_B to F and
+ * sign * (lever + node) x (...) to T, lever = offset of A's centre from the
+ * particle whose force is summed. */
+static void node_side(const opart *A, const opart *B, const double *e, double zeta, double K, double sign,
+                      const double *lever, double *F, double *T) {
+    double RA[3][3], RB[3][3];
+    quat_to_rot(A->q, RA);
+    quat_to_rot(B->q, RB);
+    const int M = g_contact_nodes;
+    for (int m = 0; m < M; ++m) {
+        double b[3], n[3], a, s[3], y[3], yb[3];
+        surface_node(A, m, M, b, n, &a);
+        rot_apply(RA, b, s);
+        for (int k = 0; k < 3; ++k) y[k] = s[k] - e[k];
+        rot_apply_t(RB, y, yb);
+        const double d = orc_sdf(B->shape, B->prm, yb);
+        if (!(d < zeta)) continue;
+        double gb[3], g[3], f[3], r[3];
+        sdf_normal(B, yb, gb);
+        rot_apply(RB, gb, g);
+        const double w = 0.5 * K * a * (zeta - d);
+        for (int k = 0; k < 3; ++k) {
+            f[k] = w * g[k];
+            F[k] += sign * f[k];
+            r[k] = lever[k] + s[k];
+        }
+        add_cross(r, f, sign, T);
+    }
+}
+
 void orc_contact_forces(const ocfg *cfg, int np, const opart *P, double range, double k, double kw,
-                        double *Fc) {
+                        double *Fc, double *Tc) {
     for (int p = 0; p < np; ++p) {
-        double acc[3] = {0.0, 0.0, 0.0};
-        if (P[p].shape == SH_SPHERE && range > 0.0) {
-            const double Rp = P[p].prm[0];
+        double acc[3] = {0.0, 0.0, 0.0}, tor[3] = {0.0, 0.0, 0.0};
+        if (range > 0.0) {
+            const double rcp = orc_circumradius(P[p].shape, P[p].prm);
             for (int q = 0; q < np; ++q) {
-                if (q == p || P[q].shape != SH_SPHERE) continue;
+                if (q == p) continue;
                 double dx[3];
                 for (int a = 0; a < 3; ++a) {
                     dx[a] = P[p].X[a] - P[q].X[a];
                     if (cfg->bc[a] == 0) dx[a] -= cfg->n[a] * round(dx[a] / cfg->n[a]);
                 }
                 const double d = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
-                const double reach = Rp + P[q].prm[0] + range;
-                if (!(d < reach) || d == 0.0) continue;
-                const double s = (reach - d) / range;
-                for (int a = 0; a < 3; ++a) acc[a] += k * s * s * dx[a] / d;
+                if (P[p].shape == SH_SPHERE && P[q].shape == SH_SPHERE) {
+                    const double reach = P[p].prm[0] + P[q].prm[0] + range;
+                    if (!(d < reach) || d == 0.0) continue;
+                    const double s = (reach - d) / range;
+                    for (int a = 0; a < 3; ++a) acc[a] += k * s * s * dx[a] / d;
+                    continue;
+                }
+                if (!(d < rcp + orc_circumradius(P[q].shape, P[q].prm) + range) || k == 0.0) continue;
+                const double Rp = vol_radius(&P[p]), Rq = vol_radius(&P[q]);
+                const double K = k / (M_PI * (Rp * Rq / (Rp + Rq)) * range * range);
+                const double e[3] = {-dx[0], -dx[1], -dx[2]}, zero[3] = {0.0, 0.0, 0.0};
+                /* nodes of p in the grown q: force on p along grad d_q */
+                node_side(&P[p], &P[q], e, range, K, 1.0, zero, acc, tor);
+                /* nodes of q in the grown p: force on q along grad d_p, minus
+                 * that on p; q's nodes sit at e + node from p's centre */
+                const double me[3] = {dx[0], dx[1], dx[2]};
+                node_side(&P[q], &P[p], me, range, K, -1.0, e, acc, tor);
             }
             for (int a = 0; a < 3; ++a) {
-                if (cfg->bc[a] == 0) continue;
-                const double dlo = 2.0 * P[p].X[a], dhi = 2.0 * (cfg->n[a] - P[p].X[a]);
-                const double reach = 2.0 * Rp + range;
-                if (dlo < reach) {
-                    const double s = (reach - dlo) / range;
-                    acc[a] += kw * s * s;
+                if (cfg->bc[a] == 0 || kw == 0.0) continue;
+                if (P[p].shape == SH_SPHERE) {
+                    const double Rp = P[p].prm[0];
+                    const double dlo = 2.0 * P[p].X[a], dhi = 2.0 * (cfg->n[a] - P[p].X[a]);
+                    const double reach = 2.0 * Rp + range;
+                    if (dlo < reach) {
+                        const double s = (reach - dlo) / range;
+                        acc[a] += kw * s * s;
+                    }
+                    if (dhi < reach) {
+                        const double s = (reach - dhi) / range;
+                        acc[a] -= kw * s * s;
+                    }
+                    continue;
                 }
-                if (dhi < reach) {
-                    const double s = (reach - dhi) / range;
-                    acc[a] -= kw * s * s;
+                if (!(P[p].X[a] < rcp + 0.5 * range || cfg->n[a] - P[p].X[a] < rcp + 0.5 * range)) continue;
+                const double Kw = kw / (M_PI * 0.5 * vol_radius(&P[p]) * range * range);
+                double R[3][3];
+                quat_to_rot(P[p].q, R);
+                const int M = g_contact_nodes;
+                for (int side = 0; side < 2; ++side) {
+                    for (int m = 0; m < M; ++m) {
+                        double b[3], n[3], w, s[3];
+                        surface_node(&P[p], m, M, b, n, &w);
+                        rot_apply(R, b, s);
+                        const double pos = P[p].X[a] + s[a];
+                        const double h = side == 0 ? pos : cfg->n[a] - pos;
+                        const double delta = range - 2.0 * h;
+                        if (!(delta > 0.0)) continue;
+                        double f[3] = {0.0, 0.0, 0.0};
+                        f[a] = (side == 0 ? 1.0 : -1.0) * Kw * w * delta;
+                        acc[a] += f[a];
+                        add_cross(s, f, 1.0, tor);
+                    }
                 }
             }
         }
-        for (int a = 0; a < 3; ++a) Fc[3 * p + a] = acc[a];
+        for (int a = 0; a < 3; ++a) {
+            Fc[3 * p + a] = acc[a];
+            if (Tc) Tc[3 * p + a] = tor[a];
+        }
     }
 }
 
@@ -678,15 +839,19 @@ int orc_run(const ocfg *cfg, int np, opart *P, double *f, int nsteps, double *Fl
     double *F = (double *)calloc((size_t)(np > 0 ? np : 1) * 3, sizeof(double));
     double *T = (double *)calloc((size_t)(np > 0 ? np : 1) * 3, sizeof(double));
     double *Fc = (double *)calloc((size_t)(np > 0 ? np : 1) * 3, sizeof(double));
+    double *Tc = (double *)calloc((size_t)(np > 0 ? np : 1) * 3, sizeof(double));
     const int contact = g_contact_range > 0.0 && (g_contact_k != 0.0 || g_contact_kw != 0.0);
     for (int s = 0; s < nsteps; ++s) {
         orc_mea(cfg, np, P, f, F, T);
         if (contact) {
-            /* the equations of motion take F + F_contact; F stays the
-             * hydrodynamic force that is reported */
-            orc_contact_forces(cfg, np, P, g_contact_range, g_contact_k, g_contact_kw, Fc);
-            for (int i = 0; i < 3 * np; ++i) Fc[i] = F[i] + Fc[i];
-            orc_apply_eom(cfg, np, P, Fc, T);
+            /* the equations of motion take F + F_contact and T + T_contact;
+             * F and T stay the hydrodynamic ones that are reported */
+            orc_contact_forces(cfg, np, P, g_contact_range, g_contact_k, g_contact_kw, Fc, Tc);
+            for (int i = 0; i < 3 * np; ++i) {
+                Fc[i] = F[i] + Fc[i];
+                Tc[i] = T[i] + Tc[i];
+            }
+            orc_apply_eom(cfg, np, P, Fc, Tc);
         } else {
             orc_apply_eom(cfg, np, P, F, T);
         }
@@ -696,7 +861,7 @@ int orc_run(const ocfg *cfg, int np, opart *P, double *f, int nsteps, double *Fl
     }
     if (Flast && nsteps > 0) memcpy(Flast, F, sizeof(double) * 3 * np);
     if (Tlast && nsteps > 0) memcpy(Tlast, T, sizeof(double) * 3 * np);
-    free(fs); free(B); free(us); free(F); free(T); free(Fc);
+    free(fs); free(B); free(us); free(F); free(T); free(Fc); free(Tc);
     return 0;
 }
 

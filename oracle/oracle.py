@@ -64,7 +64,8 @@ def lib():
         L.orc_set_mesh.argtypes = [dp, ctypes.c_int]
         L.orc_set_contact.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_contact_forces.argtypes = [cp, ctypes.c_int, vp, ctypes.c_double, ctypes.c_double,
-                                         ctypes.c_double, dp]
+                                         ctypes.c_double, dp, dp]
+        L.orc_set_contact_nodes.argtypes = [ctypes.c_int]
         L.orc_circumradius.argtypes = [ctypes.c_int, dp]
         L.orc_circumradius.restype = ctypes.c_double
         L.orc_indicator.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -258,14 +259,20 @@ class Oracle:
                       int(nsteps), F.ctypes.data, T.ctypes.data)
         return F[:len(P)], T[:len(P)]
 
-    def contact_forces(self, P, contact=None):
-        """Sphere contact forces [np, 3] on the state P (the repulsion the
-        equations of motion add when contact is set)."""
+    def contact_forces(self, P, contact=None, torque=False):
+        """Contact forces [np, 3] on the state P (the repulsion the equations
+        of motion add when contact is set); with torque, (forces, torques)."""
         rng, k, kw = (float(v) for v in (contact or self.contact))
         Fc = np.zeros((max(len(P), 1), 3))
+        Tc = np.zeros((max(len(P), 1), 3))
         lib().orc_contact_forces(ctypes.byref(self.cfg), len(P), P.ctypes.data if len(P) else None, rng, k, kw,
-                                 _dp(Fc))
-        return Fc[:len(P)]
+                                 _dp(Fc), _dp(Tc))
+        return (Fc[:len(P)], Tc[:len(P)]) if torque else Fc[:len(P)]
+
+    @staticmethod
+    def set_contact_nodes(M):
+        """Surface nodes per particle of the non-spherical contact (1024)."""
+        lib().orc_set_contact_nodes(int(M))
 
     def fields(self, P, f):
         rho = np.zeros(self.N)

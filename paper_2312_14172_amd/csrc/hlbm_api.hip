@@ -50,6 +50,7 @@ size_t pop_bytes(int precision) { return precision == HLBM_FP64 ? 8 : (precision
 
 struct Layout {
   size_t fA, fB, parts, order, stage_parts, tcnt[2], tlist[2], partial, contact, status, stage, total;
+  size_t cshapes, cdirs;  // contact records of non-spherical particles, node directions
   // learned indicator (cfg.learned)
   size_t theta[NFAM], mom1[NFAM], mom2[NFAM], packed[NFAM], gpart, gout, pool, epts, eout, tables, mesh;
   size_t band[NFAM];  // band grids (learned or mesh shapes)
@@ -128,6 +129,8 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
   }
   y.partial = off; off += align_up(np * LMAX_CAP * 6 * sizeof(double));
   y.contact = off; off += align_up(np * (size_t)contact_chunks((int)np) * 3 * sizeof(double));
+  y.cshapes = off; off += align_up(np * 6 * sizeof(double));
+  y.cdirs = off; off += align_up((size_t)CONTACT_NODES * 3 * sizeof(double));
   y.status = off; off += 256;
   // staging: 4 FP64 planes for host transfers, or the 7-double tile records
   // of the mean-velocity reduction and their sums
@@ -179,6 +182,9 @@ struct hlbm_ctx {
   int cur;            // tile-list buffer describing the current particles
   double *partial, *stage;
   double *contact;    // per-chunk sphere contact forces [chunk][n][3]
+  double *cshapes;    // contact force and torque of pairs with a non-spherical particle [n][6]
+  double *cdirs;      // surface-node directions of that contact [CONTACT_NODES][3]
+  bool nonspherical;  // the current particles include non-spherical ones
   ContactParams cparams;
   int lmax;           // z-layers of the largest momentum-exchange box
   int n;
@@ -315,6 +321,9 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   c->cur = 0;
   c->partial = (double *)(c->base + lay.partial);
   c->contact = (double *)(c->base + lay.contact);
+  c->cshapes = (double *)(c->base + lay.cshapes);
+  c->cdirs = (double *)(c->base + lay.cdirs);
+  c->nonspherical = false;
   c->cparams = ContactParams{0.0, 0.0, 0.0, 0};
   c->lmax = 1;
   c->status = (int *)(c->base + lay.status);
@@ -364,6 +373,19 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   if (e == hipSuccess) e = launch_fill_int(c->tcnt[0], 0, L.ntiles, c->stream);
   if (e == hipSuccess) e = launch_fill_int(c->tcnt[1], 0, L.ntiles, c->stream);
   if (e == hipSuccess) e = launch_fill_int(c->status, 0, 1, c->stream);
+  // surface-node directions of the non-spherical contact: a Fibonacci lattice
+  // on the unit sphere, z_m = 1 - (2 m + 1) / M, azimuth m times the golden
+  // angle pi (3 - sqrt 5)
+  std::vector<double> dirs((size_t)3 * CONTACT_NODES);
+  for (int m = 0; m < CONTACT_NODES; ++m) {
+    const double z = 1.0 - (2.0 * m + 1.0) / CONTACT_NODES, r = sqrt(std::max(0.0, 1.0 - z * z));
+    const double ph = m * (M_PI * (3.0 - sqrt(5.0)));
+    dirs[3 * m] = r * cos(ph);
+    dirs[3 * m + 1] = r * sin(ph);
+    dirs[3 * m + 2] = z;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->cdirs, dirs.data(), sizeof(double) * dirs.size(), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     delete c;
@@ -524,7 +546,11 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
   }
   ctx->n = n;
   ctx->mesh_particles = false;
-  for (int i = 0; i < n; ++i) ctx->mesh_particles |= host[i].shape == HLBM_MESH;
+  ctx->nonspherical = false;
+  for (int i = 0; i < n; ++i) {
+    ctx->mesh_particles |= host[i].shape == HLBM_MESH;
+    ctx->nonspherical |= host[i].shape != HLBM_SPHERE;
+  }
   ctx->mea_chunked = chunked ? 1 : 0;
   ctx->bin_cap = cap;
   ctx->lmax = lmax;
@@ -570,8 +596,12 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
       HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers, ctx->mea_chunked,
                          ctx->partial, s));
       HIP_TRY(launch_contact(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->contact, s));
+      const bool shapes = ctx->cparams.on && ctx->nonspherical;
+      if (shapes)
+        HIP_TRY(launch_contact_shapes(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->cdirs, ctx->cshapes, s));
       HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, layers, ctx->partial, ctx->cparams,
-                             ctx->contact, ctx->tcnt[nxt], ctx->tlist[nxt], ctx->status, s));
+                             ctx->contact, shapes ? ctx->cshapes : nullptr, ctx->tcnt[nxt], ctx->tlist[nxt],
+                             ctx->status, s));
       int rc = refresh_tables(ctx);
       if (rc) return rc;
     }

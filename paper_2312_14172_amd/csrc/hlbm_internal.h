@@ -45,9 +45,15 @@ __host__ __device__ inline int contact_chunks(int n) {
 // per-chunk contact forces out[chunk][n][3] from the state before the EoM
 hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c, double *out,
                           hipStream_t s);
+// contact of pairs with a non-spherical particle and of such particles with
+// walls: out[p] = (F, T); dirs = CONTACT_NODES unit directions (x, y, z)
+constexpr int CONTACT_NODES = 1024;
+hipError_t launch_contact_shapes(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c,
+                                 const double *dirs, double *out, hipStream_t s);
+// shapes: the records of launch_contact_shapes, or NULL
 hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, const double *partial,
-                          const ContactParams &c, const double *contact, int *tcnt, int *tlist, int *status,
-                          hipStream_t s);
+                          const ContactParams &c, const double *contact, const double *shapes, int *tcnt, int *tlist,
+                          int *status, hipStream_t s);
 hipError_t launch_collide(int prec, const Lattice &L, const void *A, void *B, const DevParticle *parts,
                           const int *tcnt, const int *tlist, int *tcnt_clear, int *status, hipStream_t s);
 hipError_t launch_set_fields(int prec, const Lattice &L, void *A, const double *rho, const double *u,

