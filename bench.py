@@ -23,7 +23,10 @@ Prints one JSON line.  Besides the throughput it carries:
                    per-particle force RMS-relative over particles, settling
                    velocity (mean U_z over particles, over the last 10 % of
                    the steps) relative;
-  cpu_baseline  -- the FP64 CPU oracle on a bounded sample of the workload.
+  cpu_baseline  -- the FP64 CPU oracle on a bounded sample of the workload;
+  segments      -- the K timed steps as 5 equal consecutive segments (stream
+                   events between them, no host synchronisation): ms per step
+                   of each and their median.
 """
 from __future__ import annotations
 
@@ -224,11 +227,19 @@ def main():
     torch.cuda.synchronize()
 
     sim.profile_begin()
+    # the K steps run as 5 equal segments between stream events (no host
+    # synchronisation inside the timed region), for a median over segments
+    nseg = 5 if args.steps >= 5 and args.steps % 5 == 0 else 1
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(nseg + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps)
+    marks[0].record()
+    for k in range(nseg):
+        sim.step(args.steps // nseg)
+        marks[k + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    seg_ms = [marks[k].elapsed_time(marks[k + 1]) / (args.steps // nseg) for k in range(nseg)]
     collide_ms, launches = sim.profile_end()
     sim.get_forces()            # surfaces any kernel-raised error of the timed steps
     dt = t1 - t0
@@ -271,6 +282,10 @@ def main():
                    "particles": int(len(wl.particles)), "solid_fraction": round(wl.solid_fraction, 4),
                    "tau": wl.tau, "storage": precision, "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu,
+        "segments": {"count": nseg, "steps_each": args.steps // nseg,
+                     "ms_per_step": [round(v, 5) for v in seg_ms],
+                     "median_ms_per_step": round(float(np.median(seg_ms)), 5),
+                     "median_mlups": round(wl.ncells / (float(np.median(seg_ms)) * 1e-3) / 1e6, 2)},
     }
     out.update(extra)
     if train_reports:
