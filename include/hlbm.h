@@ -127,7 +127,7 @@ typedef struct hlbm_particle {
     double vel[3];     /* velocity of the centre of mass */
     double omega[3];   /* angular velocity, world frame */
     double mass;       /* > 0; <= 0 holds the particle fixed at its state */
-    double volume;     /* volume used for buoyancy */
+    double volume;     /* volume (> 0), used for buoyancy and the contact stiffness */
     double inertia[3]; /* principal moments of inertia in the body frame, > 0 */
     double param[3];   /* shape parameters, see HLBM_SPHERE etc. */
     int32_t shape;     /* HLBM_SPHERE | HLBM_ROUNDED_CUBE | HLBM_SPHEROID | HLBM_MESH */
@@ -155,8 +155,8 @@ int hlbm_destroy(hlbm_ctx *ctx);
  * the particle data of Sec. 4.2 (communication of particle data: position,
  * orientation, velocity, angular
  * velocity, shape).  Checks: n <= max_particles; finite values; unit
- * quaternion (|q| within 1e-6 of 1, renormalised); inertia > 0; positive
- * shape parameters; a particle's reach (circumradius + max(eps/2, sqrt 2) + 1)
+ * quaternion (|q| within 1e-6 of 1, renormalised); inertia > 0; volume > 0;
+ * positive shape parameters; a particle's reach (circumradius + max(eps/2, sqrt 2) + 1)
  * below half of every periodic extent; centres inside the domain on wall
  * axes; circumradius below about 27 cells (the tile binning's limit). */
 int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host);

@@ -449,6 +449,7 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
       for (int k = 0; k < lens[a]; ++k)
         if (!isfinite(vals[a][k])) return fail(HLBM_EINVAL, "particle %d: non-finite value", i);
     if (!isfinite(p.mass) || !isfinite(p.volume)) return fail(HLBM_EINVAL, "particle %d: non-finite mass", i);
+    if (!(p.volume > 0.0)) return fail(HLBM_EINVAL, "particle %d: volume must be > 0", i);
     if (p.shape < HLBM_SPHERE || p.shape > HLBM_MESH) return fail(HLBM_EINVAL, "particle %d: bad shape", i);
     if (p.shape == HLBM_MESH && ctx->L.mesh_nt == 0)
       return fail(HLBM_ESTATE, "particle %d: HLBM_MESH particle but no mesh (hlbm_set_mesh)", i);
