@@ -247,8 +247,9 @@ class Simulation:
         _check(lib().hlbm_set_fluid_accel(self._ctx, a.ctypes.data))
 
     def set_contact(self, range_, stiffness, wall_stiffness=0.0):
-        """Sphere repulsion (range, pair stiffness, wall stiffness) from the
-        next step on; range 0 turns it off."""
+        """Contact repulsion (range, pair stiffness, wall stiffness) from the
+        next step on, for spheres and non-spherical shapes; range 0 turns it
+        off."""
         _check(lib().hlbm_set_contact(self._ctx, float(range_), float(stiffness), float(wall_stiffness)))
 
     def get_forces(self):

@@ -106,7 +106,7 @@ def run_periodic(phi, N=12, Ar=1500.0, ratio=1.3, tau=0.55, t_total=300.0, t_avg
     correlated than single samples), the three correlations, the residual
     volume flux and the wall time.
 
-    contact = (range, factor) turns on the sphere repulsion of the library
+    contact = (range, factor) turns on the contact repulsion of the library
     (hlbm_set_contact) with that range in cells and a stiffness of `factor`
     times one sphere's submerged weight (the force at touching)."""
     import torch

@@ -234,3 +234,40 @@ def test_shape_contact_matches_oracle_fp64(H, oracle_mod):
     np.testing.assert_allclose(st["pos"], P["X"], rtol=0, atol=1e-11)
     np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-9 * np.max(np.abs(Fo)))
     np.testing.assert_allclose(T, To, rtol=0, atol=1e-8 * np.max(np.abs(To)))
+
+
+def test_tilted_cube_settles_flat_on_wall(H):
+    """A heavy rounded cube released 30 degrees tilted above the bottom wall
+    lands on an edge; the node contact pushes that edge up off the centre
+    line, the torque turns the cube onto a face, and it comes to rest there:
+    one body axis ends within a few degrees of the wall normal, and the centre
+    height approaches the face half-size plus about half the range (the
+    flat face carries the submerged weight W = k_w A (range - 2 gap) /
+    (pi R_eq / 2 range^2) with the face area A = (2 (h - r))^2 plus the rim)."""
+    n, bc, g, ratio = (32, 32, 40), (0, 0, 1), 2e-4, 3.0
+    prm = (3.0, 0.6, 0.0)
+    ang = np.radians(30.0)
+    quat = (np.cos(ang / 2), np.sin(ang / 2) / np.sqrt(2), np.sin(ang / 2) / np.sqrt(2), 0.0)
+    rec = W.make_particle(W.ROUNDED_CUBE, prm, (16.0, 16.0, 8.0), quat=quat, density_ratio=ratio)
+    weight = (ratio - 1.0) * rec["volume"] * g
+    rng, kw = 2.5, 16.0 * weight
+    sim = H.Simulation(n, bc, 0.8, "fp64", max_particles=1, gravity=(0.0, 0.0, -g))
+    sim.set_particles(np.array([rec]))
+    sim.set_contact(rng, 0.0, kw)
+    tilts, zs = [], []
+    for _ in range(40):
+        sim.step(150)
+        _, _, st = sim.get_forces()
+        w, x, y, z = st["quat"][0]
+        # body axes in the world frame: columns of R(q); the tilt is the angle
+        # of the axis nearest to z
+        Rz = np.array([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)])
+        tilts.append(float(np.degrees(np.arccos(min(1.0, np.abs(Rz).max())))))
+        zs.append(float(st["pos"][0][2]))
+    sim.close()
+    _log(f"  tilt (deg) {np.round(tilts[::5], 2)}  heights {np.round(zs[::5], 3)}  "
+         f"speed {np.abs(st['vel'][0]).max():.2e}  spin {np.abs(st['omega'][0]).max():.2e}")
+    assert tilts[0] > 10.0
+    assert tilts[-1] < 3.0
+    assert np.abs(st["vel"][0]).max() < 1e-4 and np.abs(st["omega"][0]).max() < 1e-4
+    assert prm[0] < zs[-1] < prm[0] + rng
