@@ -50,7 +50,7 @@ size_t pop_bytes(int precision) { return precision == HLBM_FP64 ? 8 : (precision
 
 struct Layout {
   size_t fA, fB, parts, order, stage_parts, tcnt[2], tlist[2], partial, contact, status, stage, total;
-  size_t cshapes, cdirs;  // contact records of non-spherical particles, node directions
+  size_t cshapes, cdirs, ccand, ccnt;  // node contact: records, node directions, partner lists and counts
   // learned indicator (cfg.learned)
   size_t theta[NFAM], mom1[NFAM], mom2[NFAM], packed[NFAM], gpart, gout, pool, epts, eout, tables, mesh;
   size_t band[NFAM];  // band grids (learned or mesh shapes)
@@ -131,6 +131,8 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
   y.contact = off; off += align_up(np * (size_t)contact_chunks((int)np) * 3 * sizeof(double));
   y.cshapes = off; off += align_up(np * 6 * sizeof(double));
   y.cdirs = off; off += align_up((size_t)CONTACT_NODES * 3 * sizeof(double));
+  y.ccand = off; off += align_up(np * CONTACT_CAND * sizeof(int));
+  y.ccnt = off; off += align_up(np * sizeof(int));
   y.status = off; off += 256;
   // staging: 4 FP64 planes for host transfers, or the 7-double tile records
   // of the mean-velocity reduction and their sums
@@ -184,6 +186,7 @@ struct hlbm_ctx {
   double *contact;    // per-chunk sphere contact forces [chunk][n][3]
   double *cshapes;    // contact force and torque of pairs with a non-spherical particle [n][6]
   double *cdirs;      // surface-node directions of that contact [CONTACT_NODES][3]
+  int *ccand, *ccnt;  // its partner lists [n][CONTACT_CAND] and counts (zero between steps)
   bool nonspherical;  // the current particles include non-spherical ones
   ContactParams cparams;
   int lmax;           // z-layers of the largest momentum-exchange box
@@ -223,6 +226,8 @@ int check_status(hlbm_ctx *c) {
     HIP_TRY(hipMemcpy(c->status, &zero, sizeof(int), hipMemcpyHostToDevice));
     if (st & ST_TILE_OVERFLOW)
       return fail(HLBM_EUNSUPPORTED, "more than %d particles touch one 64x4x4 tile", MAXC);
+    if (st & ST_CONTACT_OVERFLOW)
+      return fail(HLBM_EUNSUPPORTED, "a non-spherical particle has more than %d contact partners", CONTACT_CAND);
     if (st & ST_WALL_EXIT) return fail(HLBM_EUNSTABLE, "a particle centre left the domain through a wall");
     return fail(HLBM_EUNSTABLE, "non-finite or non-positive density, or |u| > 0.3");
   }
@@ -323,6 +328,8 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   c->contact = (double *)(c->base + lay.contact);
   c->cshapes = (double *)(c->base + lay.cshapes);
   c->cdirs = (double *)(c->base + lay.cdirs);
+  c->ccand = (int *)(c->base + lay.ccand);
+  c->ccnt = (int *)(c->base + lay.ccnt);
   c->nonspherical = false;
   c->cparams = ContactParams{0.0, 0.0, 0.0, 0};
   c->lmax = 1;
@@ -373,6 +380,7 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   if (e == hipSuccess) e = launch_fill_int(c->tcnt[0], 0, L.ntiles, c->stream);
   if (e == hipSuccess) e = launch_fill_int(c->tcnt[1], 0, L.ntiles, c->stream);
   if (e == hipSuccess) e = launch_fill_int(c->status, 0, 1, c->stream);
+  if (e == hipSuccess) e = launch_fill_int(c->ccnt, 0, std::max(cfg->max_particles, 1), c->stream);
   // surface-node directions of the non-spherical contact: a Fibonacci lattice
   // on the unit sphere, z_m = 1 - (2 m + 1) / M, azimuth m times the golden
   // angle pi (3 - sqrt 5)
@@ -596,10 +604,12 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
       const int layers = ctx->n >= 1000 ? 4 : 2;
       HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers, ctx->mea_chunked,
                          ctx->partial, s));
-      HIP_TRY(launch_contact(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->contact, s));
+      HIP_TRY(launch_contact(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->contact, ctx->ccand, ctx->ccnt,
+                             ctx->status, s));
       const bool shapes = ctx->cparams.on && ctx->nonspherical;
       if (shapes)
-        HIP_TRY(launch_contact_shapes(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->cdirs, ctx->cshapes, s));
+        HIP_TRY(launch_contact_shapes(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->cdirs, ctx->ccand, ctx->ccnt,
+                                      ctx->cshapes, s));
       HIP_TRY(launch_eom_bin(ctx->L, ctx->parts, ctx->n, ctx->lmax, layers, ctx->partial, ctx->cparams,
                              ctx->contact, shapes ? ctx->cshapes : nullptr, ctx->tcnt[nxt], ctx->tlist[nxt],
                              ctx->status, s));

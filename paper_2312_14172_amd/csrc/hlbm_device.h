@@ -58,6 +58,7 @@ __device__ inline int wave_min(int v) {
 constexpr int ST_UNSTABLE = 1;
 constexpr int ST_WALL_EXIT = 2;
 constexpr int ST_TILE_OVERFLOW = 4;
+constexpr int ST_CONTACT_OVERFLOW = 8;
 
 struct Lattice {
   int nx, ny, nz;

@@ -43,13 +43,16 @@ __host__ __device__ inline int contact_chunks(int n) {
   return n < 1 ? 1 : (n > CONTACT_MAX_CHUNKS ? CONTACT_MAX_CHUNKS : n);
 }
 // per-chunk contact forces out[chunk][n][3] from the state before the EoM
+// cand / ccnt: partner lists of pairs with a non-spherical particle (appended)
 hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c, double *out,
-                          hipStream_t s);
+                          int *cand, int *ccnt, int *status, hipStream_t s);
 // contact of pairs with a non-spherical particle and of such particles with
-// walls: out[p] = (F, T); dirs = CONTACT_NODES unit directions (x, y, z)
+// walls: out[p] = (F, T); dirs = CONTACT_NODES unit directions (x, y, z);
+// cand / ccnt: the partner lists k_contact fills (emptied here)
 constexpr int CONTACT_NODES = 1024;
+constexpr int CONTACT_CAND = 64;  // partners of one particle in the node contact
 hipError_t launch_contact_shapes(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c,
-                                 const double *dirs, double *out, hipStream_t s);
+                                 const double *dirs, int *cand, int *ccnt, double *out, hipStream_t s);
 // shapes: the records of launch_contact_shapes, or NULL
 hipError_t launch_eom_bin(const Lattice &L, DevParticle *parts, int n, int lmax, int layers, const double *partial,
                           const ContactParams &c, const double *contact, const double *shapes, int *tcnt, int *tlist,

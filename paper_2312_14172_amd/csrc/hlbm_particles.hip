@@ -462,22 +462,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST::kind ==
 // of centres with k ((R_p + R_q + range - d) / range)^2.  Workgroup (bp, c)
 // takes 256 particles p and the c-th of up to 64 contiguous chunks of
 // partners q (enough workgroups to fill the chip for a few hundred
-// particles), staged in LDS 1024 at a time as (X, R) with R < 0 for other
-// shapes; each thread sums its chunk in increasing q into out[c][p].  O(n^2)
-// pair tests without a neighbour structure; a pair out of range costs a
-// squared distance and one compare.
+// particles), staged in LDS 1024 at a time as (X, w) with w = R for spheres
+// and -R_circ for other shapes; each thread sums its chunk in increasing q
+// into out[c][p].  Pairs with a non-spherical particle whose bounding
+// spheres come within the range are appended to p's candidate list
+// (cand[p][0 .. CONTACT_CAND), count ccnt[p]) for k_contact_shapes, in no
+// fixed order (that kernel sorts them).  O(n^2) pair tests without a
+// neighbour structure; a pair out of range costs a squared distance and one
+// compare.
 __global__ __launch_bounds__(256) void k_contact(Lattice L, const DevParticle *__restrict__ parts, int n,
-                                                 ContactParams c, double *__restrict__ out) {
+                                                 ContactParams c, double *__restrict__ out, int *__restrict__ cand,
+                                                 int *__restrict__ ccnt, int *status) {
   __shared__ double4 sq[CONTACT_TILE];
   const int nchunk = gridDim.y;
   const int per = (n + nchunk - 1) / nchunk;
   const int q_begin = blockIdx.y * per, q_end = min(n, q_begin + per);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int nn[3] = {L.nx, L.ny, L.nz};
-  double Xp[3] = {0, 0, 0}, Rp = -1.0;
-  if (p < n && parts[p].shape == 0) {
+  double Xp[3] = {0, 0, 0}, wp = 0.0;
+  if (p < n) {
     for (int a = 0; a < 3; ++a) Xp[a] = parts[p].X[a];
-    Rp = parts[p].prm[0];
+    wp = parts[p].shape == 0 ? parts[p].prm[0] : -parts[p].rc;
   }
   double acc[3] = {0.0, 0.0, 0.0};
   for (int t0 = q_begin; t0 < q_end; t0 += CONTACT_TILE) {
@@ -485,22 +490,28 @@ __global__ __launch_bounds__(256) void k_contact(Lattice L, const DevParticle *_
     __syncthreads();
     for (int j = threadIdx.x; j < nt; j += blockDim.x) {
       const DevParticle &q = parts[t0 + j];
-      sq[j] = make_double4(q.X[0], q.X[1], q.X[2], q.shape == 0 ? q.prm[0] : -1.0);
+      sq[j] = make_double4(q.X[0], q.X[1], q.X[2], q.shape == 0 ? q.prm[0] : -q.rc);
     }
     __syncthreads();
-    if (Rp > 0.0) {
+    if (p < n) {
       for (int j = 0; j < nt; ++j) {
         const double4 v = sq[j];
-        if (t0 + j == p || v.w < 0.0) continue;
+        if (t0 + j == p) continue;
         double dx[3] = {Xp[0] - v.x, Xp[1] - v.y, Xp[2] - v.z};
         for (int a = 0; a < 3; ++a)  // minimum image (centres lie in [0, n) on periodic axes)
           if (!L.bc[a]) dx[a] = dx[a] > 0.5 * nn[a] ? dx[a] - nn[a] : (dx[a] < -0.5 * nn[a] ? dx[a] + nn[a] : dx[a]);
-        const double reach = Rp + v.w + c.range;
+        const double reach = fabs(wp) + fabs(v.w) + c.range;
         const double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
         if (!(d2 < reach * reach) || d2 == 0.0) continue;
-        const double d = sqrt(d2);
-        const double sc = (reach - d) / c.range;
-        for (int a = 0; a < 3; ++a) acc[a] += c.k * sc * sc * dx[a] / d;
+        if (wp > 0.0 && v.w > 0.0) {
+          const double d = sqrt(d2);
+          const double sc = (reach - d) / c.range;
+          for (int a = 0; a < 3; ++a) acc[a] += c.k * sc * sc * dx[a] / d;
+        } else if (c.k != 0.0) {
+          const int slot = atomicAdd(&ccnt[p], 1);
+          if (slot < CONTACT_CAND) cand[(size_t)p * CONTACT_CAND + slot] = t0 + j;
+          else atomicOr(status, ST_CONTACT_OVERFLOW);
+        }
       }
     }
   }
@@ -615,7 +626,8 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
 // (u . n).  Pairs of two spheres are left to k_contact.
 //
 // One wavefront per particle p: the partners (bounding spheres within the
-// range, increasing index) and then the walls; for each, the nodes whose ray
+// range, listed by k_contact; taken in increasing index) and then the walls;
+// for each, the nodes whose ray
 // segment between the inscribed and the circumscribed radius comes within
 // reach are compacted in LDS and evaluated 64 at a time.  Per-lane FP64 sums,
 // one fixed wavefront reduction at the end: record shapes[p] = (F, T).
@@ -770,6 +782,18 @@ __device__ inline int queue_nodes_near(const DevParticle &A, double rin, const d
 
 // The nodes of A probing the grown B (centre at e from A's centre): adds
 // sign * the force and sign * (lever + s) x force to F, T.
+// Support function of the body along the unit world direction v: the
+// largest (x - X) . v over the body (the circumradius for a mesh).
+__device__ inline double support(const DevParticle &P, const double *v) {
+  double b[3];
+  rot_t(P.R, v, b);
+  if (P.shape == 0) return P.prm[0];
+  if (P.shape == 1) return (P.prm[0] - P.prm[1]) * (fabs(b[0]) + fabs(b[1]) + fabs(b[2])) + P.prm[1];
+  if (P.shape == 2)
+    return sqrt(P.prm[0] * P.prm[0] * b[0] * b[0] + P.prm[1] * P.prm[1] * (b[1] * b[1] + b[2] * b[2]));
+  return P.rc;
+}
+
 template <bool MESH>
 __device__ inline void pair_side(const Lattice &L, const DevParticle &A, const DevParticle &B, const double *e,
                                  double zeta, double K, double sign, const double *lever, const double *dirs,
@@ -788,7 +812,14 @@ __device__ inline void pair_side(const Lattice &L, const DevParticle &A, const D
       rot(A.R, b, sv);
       for (int j = 0; j < 3; ++j) y[j] = sv[j] - e[j];
       rot_t(B.R, y, yb);
-      const double d = body_sdf<MESH>(L, B, yb);
+      // spheroid: the scaled spheroids s E and E (s^2 the implicit value) are
+      // at least (s - 1) min(a, b) apart, a cheap bound before the iteration
+      bool far = false;
+      if (B.shape == 2) {
+        const double kk = yb[0] * yb[0] / (B.prm[0] * B.prm[0]) + (yb[1] * yb[1] + yb[2] * yb[2]) / (B.prm[1] * B.prm[1]);
+        far = (sqrt(kk) - 1.0) * fmin(B.prm[0], B.prm[1]) >= zeta;
+      }
+      const double d = far ? zeta : body_sdf<MESH>(L, B, yb);
       if (d < zeta) {
         double gb[3], g[3];
         body_sdf_normal<MESH>(L, B, yb, gb);
@@ -810,49 +841,45 @@ __device__ inline void pair_side(const Lattice &L, const DevParticle &A, const D
 template <bool MESH>
 __global__ __launch_bounds__(64) void k_contact_shapes(Lattice L, const DevParticle *__restrict__ parts, int n,
                                                        ContactParams c, const double *__restrict__ dirs,
+                                                       int *__restrict__ cand, int *__restrict__ ccnt,
                                                        double *__restrict__ out) {
   __shared__ int queue[CONTACT_NODES];
+  __shared__ int part[CONTACT_CAND];
   const int pid = blockIdx.x, lane = threadIdx.x;
   const DevParticle &P = parts[pid];
   const int nn[3] = {L.nx, L.ny, L.nz};
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
   const double Rp = cbrt(3.0 * P.V / (4.0 * M_PI));
-  if (c.k != 0.0) {
-    for (int q0 = 0; q0 < n; q0 += 64) {
-      const int qi = q0 + lane;
-      bool cand = false;
-      if (qi < n && qi != pid) {
-        const DevParticle &Q = parts[qi];
-        if (P.shape != 0 || Q.shape != 0) {
-          double d2 = 0.0;
-          for (int a = 0; a < 3; ++a) {
-            double dx = Q.X[a] - P.X[a];
-            if (!L.bc[a]) dx = dx > 0.5 * nn[a] ? dx - nn[a] : (dx < -0.5 * nn[a] ? dx + nn[a] : dx);
-            d2 += dx * dx;
-          }
-          const double reach = P.rc + Q.rc + c.range;
-          cand = d2 < reach * reach;
-        }
-      }
-      unsigned long long mask = __ballot(cand);
-      while (mask) {  // partners in increasing index (uniform)
-        const int qj = q0 + __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        const DevParticle &Q = parts[qj];
-        double e[3], me[3];
-        for (int a = 0; a < 3; ++a) {
-          double dx = Q.X[a] - P.X[a];
-          if (!L.bc[a]) dx = dx > 0.5 * nn[a] ? dx - nn[a] : (dx < -0.5 * nn[a] ? dx + nn[a] : dx);
-          e[a] = dx;
-          me[a] = -dx;
-        }
-        const double Rq = cbrt(3.0 * Q.V / (4.0 * M_PI));
-        const double K = c.k / (M_PI * (Rp * Rq / (Rp + Rq)) * c.range * c.range);
-        const double zero[3] = {0.0, 0.0, 0.0};
-        pair_side<MESH>(L, P, Q, e, c.range, K, 1.0, zero, dirs, queue, F, T);
-        pair_side<MESH>(L, Q, P, me, c.range, K, -1.0, e, dirs, queue, F, T);
-      }
+  // partners in increasing index: the list entries ranked by value
+  const int np = min(ccnt[pid], CONTACT_CAND);
+  const int mine = lane < np ? cand[(size_t)pid * CONTACT_CAND + lane] : 0;
+  __syncthreads();
+  if (lane == 0) ccnt[pid] = 0;  // emptied for the next step's k_contact
+  if (lane < np) {
+    int rank = 0;
+    for (int k = 0; k < np; ++k) rank += cand[(size_t)pid * CONTACT_CAND + k] < mine;
+    part[rank] = mine;
+  }
+  __syncthreads();
+  for (int k = 0; k < np; ++k) {  // uniform
+    const DevParticle &Q = parts[part[k]];
+    double e[3], me[3];
+    for (int a = 0; a < 3; ++a) {
+      double dx = Q.X[a] - P.X[a];
+      if (!L.bc[a]) dx = dx > 0.5 * nn[a] ? dx - nn[a] : (dx < -0.5 * nn[a] ? dx + nn[a] : dx);
+      e[a] = dx;
+      me[a] = -dx;
     }
+    // separated along the line of centres by at least the range (support
+    // functions): no node of either body comes within the range of the other
+    const double dist = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    const double v[3] = {e[0] / dist, e[1] / dist, e[2] / dist}, mv[3] = {-v[0], -v[1], -v[2]};
+    if (dist - support(P, v) - support(Q, mv) >= c.range) continue;  // uniform
+    const double Rq = cbrt(3.0 * Q.V / (4.0 * M_PI));
+    const double K = c.k / (M_PI * (Rp * Rq / (Rp + Rq)) * c.range * c.range);
+    const double zero[3] = {0.0, 0.0, 0.0};
+    pair_side<MESH>(L, P, Q, e, c.range, K, 1.0, zero, dirs, queue, F, T);
+    pair_side<MESH>(L, Q, P, me, c.range, K, -1.0, e, dirs, queue, F, T);
   }
   if (P.shape != 0 && c.kw != 0.0) {
     const double Kw = c.kw / (M_PI * 0.5 * Rp * c.range * c.range);
@@ -960,20 +987,20 @@ hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevPartic
 }
 
 hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c, double *out,
-                          hipStream_t s) {
+                          int *cand, int *ccnt, int *status, hipStream_t s) {
   if (n <= 0 || !c.on) return hipSuccess;
   const dim3 grid(blocks_for(n, 256), contact_chunks(n));
-  hipLaunchKernelGGL(k_contact, grid, dim3(256), 0, s, L, parts, n, c, out);
+  hipLaunchKernelGGL(k_contact, grid, dim3(256), 0, s, L, parts, n, c, out, cand, ccnt, status);
   return hipGetLastError();
 }
 
 hipError_t launch_contact_shapes(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c,
-                                 const double *dirs, double *out, hipStream_t s) {
+                                 const double *dirs, int *cand, int *ccnt, double *out, hipStream_t s) {
   if (n <= 0 || !c.on) return hipSuccess;
   if (L.mesh_nt > 0)
-    hipLaunchKernelGGL(k_contact_shapes<true>, dim3(n), dim3(64), 0, s, L, parts, n, c, dirs, out);
+    hipLaunchKernelGGL(k_contact_shapes<true>, dim3(n), dim3(64), 0, s, L, parts, n, c, dirs, cand, ccnt, out);
   else
-    hipLaunchKernelGGL(k_contact_shapes<false>, dim3(n), dim3(64), 0, s, L, parts, n, c, dirs, out);
+    hipLaunchKernelGGL(k_contact_shapes<false>, dim3(n), dim3(64), 0, s, L, parts, n, c, dirs, cand, ccnt, out);
   return hipGetLastError();
 }
 
