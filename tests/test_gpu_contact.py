@@ -271,3 +271,25 @@ def test_tilted_cube_settles_flat_on_wall(H):
     assert tilts[-1] < 3.0
     assert np.abs(st["vel"][0]).max() < 1e-4 and np.abs(st["omega"][0]).max() < 1e-4
     assert prm[0] < zs[-1] < prm[0] + rng
+
+
+def test_contact_partner_list_overflow_is_reported(H):
+    """A non-spherical particle with more candidate partners than its list
+    holds (64: bounding spheres within the range) makes hlbm_step fail with
+    HLBM_EUNSUPPORTED instead of dropping partners."""
+    rng = np.random.default_rng(4)
+    n, bc = (48, 48, 48), (0, 0, 0)
+    centre = np.array([24.0, 24.0, 24.0])
+    big = W.make_particle(W.SPHEROID, (6.0, 3.0, 0.0), tuple(centre))
+    dirs = rng.normal(size=(80, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    small = [W.make_particle(W.SPHERE, (0.6,), tuple(centre + 7.5 * d)) for d in dirs]
+    parts = np.array([big] + small)
+    sim = H.Simulation(n, bc, 0.8, "fp64", max_particles=len(parts))
+    sim.set_particles(parts)
+    sim.set_contact(2.0, 1e-3, 0.0)
+    with pytest.raises(H.HLBMError) as e:
+        sim.step(1)
+        sim.get_forces()
+    assert e.value.code == -6
+    sim.close()
