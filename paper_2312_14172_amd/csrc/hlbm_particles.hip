@@ -626,11 +626,12 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
 // (u . n).  Pairs of two spheres are left to k_contact.
 //
 // One wavefront per particle p: the partners (bounding spheres within the
-// range, listed by k_contact; taken in increasing index) and then the walls;
-// for each, the nodes whose ray
-// segment between the inscribed and the circumscribed radius comes within
-// reach are compacted in LDS and evaluated 64 at a time.  Per-lane FP64 sums,
-// one fixed wavefront reduction at the end: record shapes[p] = (F, T).
+// range, listed by k_contact; taken in increasing index; pairs that the
+// support functions separate by the range along the line of centres are
+// skipped) and then the walls; for each, the nodes whose ray segment between
+// the inscribed and the circumscribed radius comes within reach are
+// compacted in LDS and evaluated 64 at a time.  Per-lane FP64 sums, one
+// fixed wavefront reduction at the end: record shapes[p] = (F, T).
 // ---------------------------------------------------------------------------
 __device__ inline double inscribed_radius(const DevParticle &P) {
   return P.shape == 2 ? fmin(P.prm[0], P.prm[1]) : (P.shape == 3 ? P.prm[2] : P.prm[0]);
