@@ -31,7 +31,7 @@ hipError_t launch_bin(const Lattice &L, const DevParticle *parts, int n, int cap
                       int *status, hipStream_t s);
 hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevParticle *parts, const int *order, int n,
                       int lmax, int layers, int chunked, double *partial, hipStream_t s);
-// sphere contact: short-range repulsion of range `range`, pair stiffness k,
+// contact: short-range repulsion of range `range`, pair stiffness k,
 // wall stiffness kw (on = range > 0 and k or kw nonzero)
 struct ContactParams {
   double range, k, kw;
