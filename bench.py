@@ -52,7 +52,7 @@ TRAIN = dict(samples=1_000_000, holdout=100_000, iterations=30000, batch=8192, l
              band=0.1, clip=0.25, band_share=0.8, gate_rms=0.05, gate_max=0.5)
 
 
-def make_sim(H, W, wl, precision):
+def make_sim(H, W, wl, precision, coupling="hlbm"):
     """A context for the workload; for a learned workload the non-spherical
     families present are trained first (outside any timed region)."""
     import numpy as np
@@ -65,7 +65,7 @@ def make_sim(H, W, wl, precision):
                        gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f,
                        learned_max_circumradius=rmax + 0.01 if (learned or mesh) else 0.0,
                        learned_samples=1_100_000 if learned else 0,
-                       max_mesh_triangles=len(W.MESH_UNIT[1]) if mesh else 0)
+                       max_mesh_triangles=len(W.MESH_UNIT[1]) if mesh else 0, coupling=coupling)
     if mesh:
         sim.set_mesh(*W.MESH_UNIT)
     reports = {}
@@ -109,7 +109,7 @@ def load_traffic(workload: str, precision: str):
     return int(rec["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in rec else None
 
 
-def errors_vs_fp64(H, wl, precision, steps, every):
+def errors_vs_fp64(H, wl, precision, steps, every, coupling="hlbm"):
     """This precision against the FP64 plain form (exact indicator) of the
     same workload from rest: velocity L2-relative and max |rho - rho_ref|
     after `steps`, the per-particle force averaged over samples every `every`
@@ -129,12 +129,12 @@ def errors_vs_fp64(H, wl, precision, steps, every):
             sim = H.Simulation(wl.n, wl.bc, wl.tau, prec, max_particles=len(wl.particles),
                                gravity=wl.gravity, eps=wl.eps, rho_f=wl.rho_f,
                                learned_max_circumradius=rmax + 0.01 if mesh else 0.0,
-                               max_mesh_triangles=len(W.MESH_UNIT[1]) if mesh else 0)
+                               max_mesh_triangles=len(W.MESH_UNIT[1]) if mesh else 0, coupling=coupling)
             if mesh:
                 sim.set_mesh(*W.MESH_UNIT)
             sim.set_particles(wl.particles)
         else:
-            sim, _ = make_sim(H, W, wl, prec)
+            sim, _ = make_sim(H, W, wl, prec, coupling)
         acc = np.zeros((len(wl.particles), 3))
         vz = []
         for k in range(nsamp):
@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="hindered384", choices=sorted(DEFAULT_PRECISION))
     ap.add_argument("--precision", default=None, choices=sorted(POP_BYTES))
+    ap.add_argument("--coupling", default="hlbm", choices=("hlbm", "psm"),
+                    help="exact-difference source (hlbm) or partially saturated collision (psm)")
     ap.add_argument("--check-steps", type=int, default=1000,
                     help="steps of the untimed runs compared with FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -221,7 +223,7 @@ def main():
     print(f"[bench] {wl.name}: {wl.n} cells, {len(wl.particles)} particles, {precision}, "
           f"phi={wl.solid_fraction:.3f}", file=sys.stderr, flush=True)
     H.lib()
-    sim, train_reports = make_sim(H, W, wl, precision)
+    sim, train_reports = make_sim(H, W, wl, precision, args.coupling)
     sim.step(args.warmup)
     sim.get_forces()            # synchronises and reports kernel errors
     torch.cuda.synchronize()
@@ -267,7 +269,7 @@ def main():
     extra = {}
     if not args.no_force_check and precision != "fp64" and len(wl.particles):
         print(f"[bench] errors against FP64: {args.check_steps} steps per precision", file=sys.stderr, flush=True)
-        extra["errors_vs_fp64"] = errors_vs_fp64(H, wl, precision, args.check_steps, 10)
+        extra["errors_vs_fp64"] = errors_vs_fp64(H, wl, precision, args.check_steps, 10, args.coupling)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -280,7 +282,7 @@ def main():
         "dtype": DTYPE[precision], "data": "synthetic",
         "config": {"workload": wl.name, "lattice": list(wl.n), "bc": list(wl.bc),
                    "particles": int(len(wl.particles)), "solid_fraction": round(wl.solid_fraction, 4),
-                   "tau": wl.tau, "storage": precision, "parallelism": "single GPU"},
+                   "tau": wl.tau, "storage": precision, "coupling": args.coupling, "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu,
         "segments": {"count": nseg, "steps_each": args.steps // nseg,
                      "ms_per_step": [round(v, 5) for v in seg_ms],

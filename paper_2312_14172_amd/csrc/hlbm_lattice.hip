@@ -33,8 +33,12 @@ __device__ inline void pull_fast(const typename ST::S *__restrict__ A, long long
   }
 }
 
+// At least 5 wavefronts per SIMD asked of the register allocator: the FP32
+// and FP16S instances then fit in 76 VGPRs (6 waves) and the partially
+// saturated ones in 96 (5 waves), which the memory-bound loop turns into
+// time (mixed256 FP16S 342 -> 321 us, hindered384 PSM 1883 -> 1778 us).
 template <class ST, bool PSM>
-__global__ __launch_bounds__(256) void k_collide(Lattice L, const typename ST::S *__restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_collide(Lattice L, const typename ST::S *__restrict__ A,
                                                  typename ST::S *__restrict__ Bo,
                                                  const DevParticle *__restrict__ parts,
                                                  const int *__restrict__ tcnt,
