@@ -952,7 +952,7 @@ int hlbm_mlp_gradient(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *pts
   const int nb = mlp_grad_blocks(n, MLP_MAX_BLOCKS);
   HIP_TRY(mlp_grad(ctx->theta[f], ctx->packed[f], ctx->pool, n, MLP_MAX_BLOCKS, 2.0f / n, ctx->gpart, ctx->stream));
   HIP_TRY(mlp_reduce_adam(ctx->theta[f], ctx->mom1[f], ctx->mom2[f], ctx->gpart, nb, ctx->gout, 0, 0.f, 1,
-                          ctx->stream));
+                          nullptr, ctx->stream));
   HIP_TRY(hipMemcpyAsync(g.data(), ctx->gout, sizeof(float) * MLP_PARTIAL, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   for (int k = 0; k < MLP_NPARAM; ++k) grad[k] = g[k];
@@ -979,8 +979,7 @@ int hlbm_mlp_train_step(hlbm_ctx *ctx, int32_t shape, int32_t n, const double *p
   const int nb = mlp_grad_blocks(n, MLP_MAX_BLOCKS);
   HIP_TRY(mlp_grad(ctx->theta[f], ctx->packed[f], ctx->pool, n, MLP_MAX_BLOCKS, 2.0f / n, ctx->gpart, ctx->stream));
   HIP_TRY(mlp_reduce_adam(ctx->theta[f], ctx->mom1[f], ctx->mom2[f], ctx->gpart, nb, ctx->gout, 1, (float)lr, step,
-                          ctx->stream));
-  HIP_TRY(mlp_pack(ctx->theta[f], ctx->packed[f], ctx->stream));
+                          ctx->packed[f], ctx->stream));
   HIP_TRY(hipMemcpyAsync(g.data(), ctx->gout, sizeof(float) * MLP_PARTIAL, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   if (grad)
@@ -1058,8 +1057,7 @@ int hlbm_train_indicator(hlbm_ctx *ctx, int32_t shape, const double *param, cons
     const bool record = it == 0 || it == o->iterations - 1;
     HIP_TRY(mlp_grad(ctx->theta[f], ctx->packed[f], batch, o->batch, MLP_MAX_BLOCKS, 2.0f / o->batch, ctx->gpart, s));
     HIP_TRY(mlp_reduce_adam(ctx->theta[f], ctx->mom1[f], ctx->mom2[f], ctx->gpart, nb, record ? ctx->gout : nullptr,
-                            1, lr, it + 1, s));
-    HIP_TRY(mlp_pack(ctx->theta[f], ctx->packed[f], s));
+                            1, lr, it + 1, ctx->packed[f], s));
     if (record) {
       float sse = 0;
       HIP_TRY(hipMemcpyAsync(&sse, ctx->gout + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToHost, s));
@@ -1184,6 +1182,6 @@ extern "C" int hlbm_mlp_gradient_noalloc(const float *d_theta, int32_t n, const 
   HIP_TRY(mlp_pack(d_theta, packed, s));
   HIP_TRY(mlp_grad(d_theta, packed, (const float4 *)d_samples, n, MLP_MAX_BLOCKS, 2.0f / n, partial, s));
   // the reduction alone (no Adam step): parameters and moments are not touched
-  HIP_TRY(mlp_reduce_adam(const_cast<float *>(d_theta), nullptr, nullptr, partial, nb, d_grad, 0, 0.f, 1, s));
+  HIP_TRY(mlp_reduce_adam(const_cast<float *>(d_theta), nullptr, nullptr, partial, nb, d_grad, 0, 0.f, 1, nullptr, s));
   return HLBM_OK;
 }

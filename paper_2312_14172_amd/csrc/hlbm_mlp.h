@@ -36,8 +36,10 @@ hipError_t mlp_eval(const float *theta, const __bf16 *packed, const float *pts, 
 hipError_t mlp_grad(const float *theta, const __bf16 *packed, const float4 *samples, int n, int nblocks,
                     float scale, float *partial, hipStream_t s);
 int mlp_grad_blocks(int n, int nblocks);
+// packed: with do_step, the packed operands to update in place (replaces a
+// k_mlp_pack launch after the step), or NULL
 hipError_t mlp_reduce_adam(float *theta, float *m, float *v, const float *partial, int nblocks, float *grad_out,
-                           int do_step, float lr, int step, hipStream_t s);
+                           int do_step, float lr, int step, __bf16 *packed, hipStream_t s);
 hipError_t mlp_samples(int shape, double p0, double p1, const float4 *mesh, int mesh_nt, uint64_t seed, int n,
                        double box, double band, double clip, double band_share, float4 *out, hipStream_t s);
 

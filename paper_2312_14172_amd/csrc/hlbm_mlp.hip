@@ -176,26 +176,30 @@ __global__ __launch_bounds__(64) void k_mlp_eval(const float *__restrict__ theta
 }
 
 // ---------------------------------------------------------------------------
-// Gradient of the mean-squared loss over a batch.  One wave per workgroup;
-// workgroup b handles samples [b*per, (b+1)*per) in pairs of 16-sample tiles
-// and writes its partial gradient (MLP_NPARAM floats) and squared-error sum.
+// Gradient of the mean-squared loss over a batch.  Two wavefronts per
+// workgroup; workgroup b handles samples [b*per, (b+1)*per) in pairs of
+// 16-sample tiles, wavefront q taking tile q of each pair, and writes its
+// partial gradient (MLP_NPARAM floats) and squared-error sum.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ theta, const __bf16 *__restrict__ packed,
-                                                 const float4 *__restrict__ samples, int n, int per, float scale,
-                                                 float *__restrict__ partial) {
+__global__ __launch_bounds__(128) void k_mlp_grad(const float *__restrict__ theta, const __bf16 *__restrict__ packed,
+                                                  const float4 *__restrict__ samples, int n, int per, float scale,
+                                                  float *__restrict__ partial) {
   __shared__ __attribute__((aligned(16))) __bf16 hT1[64][32], hT2[64][32], dT2[64][32], dT3[64][32];
+  __shared__ float xfer[114 * 64];  // wavefront 1's per-lane sums
   const MlpArgs A = mlp_args(theta, packed);
   const float *th = theta;
-  const int l = threadIdx.x, g = l >> 4, li = l & 15;
+  const int l = lane_id(), q = wave_id(), g = l >> 4, li = l & 15;
   float gW1[16][3], gb1[16], gb2[16], gb3[16], gW4[16], gb4 = 0.f, sse = 0.f;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     gW1[k][0] = gW1[k][1] = gW1[k][2] = 0.f;
     gb1[k] = gb2[k] = gb3[k] = gW4[k] = 0.f;
   }
-  f32x4 dW2[4][4], dW3[4][4];
+  // weight-gradient blocks (a, b) of the two 64x64 layers; wavefront q owns
+  // the row blocks a = 2q, 2q + 1
+  f32x4 dW2[2][4], dW3[2][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       dW2[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -204,8 +208,11 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ theta
   const int s0 = blockIdx.x * per;
   const int s1 = min(n, s0 + per);
   for (int base = s0; base < s1; base += 32) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    // the weight fragments and per-lane parameters are re-read (L1) for each
+    // tile: hoisted out of the loop they would sit beside the 176 gradient
+    // accumulators and push the kernel into scratch spills
+    __asm__ volatile("" ::: "memory");
+    {
       const int s = base + q * 16 + li;
       const bool ok = s < s1;
       const float4 smp = ok ? samples[s] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -267,10 +274,12 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ theta
     // samples of the pair, operands transposed through LDS
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const bf16x8 a3 = *(const bf16x8 *)&dT3[16 * a + li][8 * g];
-      const bf16x8 a2 = *(const bf16x8 *)&dT2[16 * a + li][8 * g];
+    for (int a = 0; a < 2; ++a) {
+      const int ra = 16 * (2 * q + a) + li;
+      const bf16x8 a3 = *(const bf16x8 *)&dT3[ra][8 * g];
+      const bf16x8 a2 = *(const bf16x8 *)&dT2[ra][8 * g];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const bf16x8 b2 = *(const bf16x8 *)&hT2[16 * b + li][8 * g];
@@ -284,21 +293,39 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ theta
   // ---- write this workgroup's partial gradient ------------------------
   float *out = partial + (size_t)blockIdx.x * MLP_PARTIAL;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int row = 16 * a + 4 * g + j, col = 16 * b + li;
+        const int row = 16 * (2 * q + a) + 4 * g + j, col = 16 * b + li;
         out[MLP_OFF_W2 + row * 64 + col] = dW2[a][b][j];
         out[MLP_OFF_W3 + row * 64 + col] = dW3[a][b][j];
       }
-  // per-feature sums over the 16 sample lanes of each lane group
+  // per-lane sums of wavefront 1 added to wavefront 0's, then per-feature
+  // sums over the 16 sample lanes of each lane group
+  if (q == 1) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      xfer[(7 * k + 0) * 64 + l] = gb1[k];
+      xfer[(7 * k + 1) * 64 + l] = gb2[k];
+      xfer[(7 * k + 2) * 64 + l] = gb3[k];
+      xfer[(7 * k + 3) * 64 + l] = gW4[k];
+      xfer[(7 * k + 4) * 64 + l] = gW1[k][0];
+      xfer[(7 * k + 5) * 64 + l] = gW1[k][1];
+      xfer[(7 * k + 6) * 64 + l] = gW1[k][2];
+    }
+    xfer[112 * 64 + l] = gb4;
+    xfer[113 * 64 + l] = sse;
+  }
+  __syncthreads();
+  if (q == 1) return;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     float v[7] = {gb1[k], gb2[k], gb3[k], gW4[k], gW1[k][0], gW1[k][1], gW1[k][2]};
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
+      v[m] += xfer[(7 * k + m) * 64 + l];
       v[m] += __shfl_xor(v[m], 1, 64);
       v[m] += __shfl_xor(v[m], 2, 64);
       v[m] += __shfl_xor(v[m], 4, 64);
@@ -315,7 +342,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ theta
       out[MLP_OFF_W1 + 3 * f + 2] = v[6];
     }
   }
-  float v4[2] = {gb4, sse};
+  float v4[2] = {gb4 + xfer[112 * 64 + l], sse + xfer[113 * 64 + l]};
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -326,21 +353,65 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ theta
   }
 }
 
+// Index within one packed 64x64 operand of the element that k_mlp_pack takes
+// from row `tile` * 16 + li of its source and contraction index k (the
+// inverse of kappa: k = 32 c + 16 (e >> 2) + 4 g + (e & 3)).
+__device__ inline int packed_index(int tile, int li, int k) {
+  const int c = k >> 5, rem = k & 31;
+  const int g = (rem & 15) >> 2, e = (rem & 3) + 4 * (rem >> 4);
+  return e + 8 * (16 * g + li) + 512 * c + 1024 * tile;
+}
+
+// Writes parameter p's value v to every place k_mlp_pack puts it (the same
+// values and roundings as a full repack; b4 is read from theta directly).
+__device__ inline void pack_param(__bf16 *__restrict__ packed, int p, float v) {
+  float *lanef = (float *)(packed + MLP_PACKED);
+  if ((p >= MLP_OFF_W2 && p < MLP_OFF_B2) || (p >= MLP_OFF_W3 && p < MLP_OFF_B3)) {
+    const int L = p >= MLP_OFF_W3;
+    const int q = p - (L ? MLP_OFF_W3 : MLP_OFF_W2), row = q >> 6, col = q & 63;
+    const __bf16 b = (__bf16)v;
+    packed[L * 4096 + packed_index(row >> 4, row & 15, col)] = b;        // forward, A = W
+    packed[(2 + L) * 4096 + packed_index(col >> 4, col & 15, row)] = b;  // backward, A = W^T
+  } else if (p < MLP_OFF_W2) {
+    // W1[f][0..2] and b1[f]: float4 slot 4 ot + j of lane group g
+    const int f = p < MLP_OFF_B1 ? p / 3 : p - MLP_OFF_B1, comp = p < MLP_OFF_B1 ? p % 3 : 3;
+    const int g = (f & 15) >> 2, slot = g * MLP_LANE_F4 + 4 * (f >> 4) + (f & 3);
+    lanef[4 * slot + comp] = v;
+  } else if (p < MLP_OFF_B4) {
+    // b2, b3, W4 [f]: component f & 3 of slot 16 / 20 / 24 + ot of group g
+    const int which = p < MLP_OFF_W3 ? 0 : (p < MLP_OFF_W4 ? 1 : 2);
+    const int f = p - (which == 0 ? MLP_OFF_B2 : (which == 1 ? MLP_OFF_B3 : MLP_OFF_W4));
+    const int g = (f & 15) >> 2, slot = g * MLP_LANE_F4 + 16 + 4 * which + (f >> 4);
+    lanef[4 * slot + (f & 3)] = v;
+  }
+}
+
 // Sum the workgroup partials in a fixed order; optionally apply one Adam step
-// (Kingma & Ba 2015, bias-corrected) to the FP32 master parameters.  One
+// (Kingma & Ba 2015, bias-corrected) to the FP32 master parameters and write
+// the updated values into the packed operands (packed != NULL).  One
 // workgroup per 64 parameters: wavefront w sums the partials w, w + 4, ...
-// of its lane's parameter, and the four wavefront sums are added in order.
+// of its lane's parameter in increasing order (the loads issued 16 at a time
+// ahead of the additions), and the four wavefront sums are added in order.
 __global__ __launch_bounds__(256) void k_mlp_reduce_adam(float *__restrict__ theta, float *__restrict__ m,
                                                          float *__restrict__ v, const float *__restrict__ partial,
                                                          int nblocks, float *__restrict__ grad_out, int do_step,
                                                          float lr, float b1, float b2, float eps, float bc1,
-                                                         float bc2) {
+                                                         float bc2, __bf16 *__restrict__ packed) {
   __shared__ float part[4][64];
   const int lane = lane_id(), w = wave_id();
   const int p = blockIdx.x * 64 + lane;
   float gs = 0.f;
-  if (p <= MLP_NPARAM)
-    for (int b = w; b < nblocks; b += 4) gs += partial[(size_t)b * MLP_PARTIAL + p];
+  if (p <= MLP_NPARAM) {
+    int b = w;
+    for (; b + 4 * 15 < nblocks; b += 4 * 16) {
+      float x[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = partial[(size_t)(b + 4 * k) * MLP_PARTIAL + p];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) gs += x[k];
+    }
+    for (; b < nblocks; b += 4) gs += partial[(size_t)b * MLP_PARTIAL + p];
+  }
   part[w][lane] = gs;
   __syncthreads();
   if (w != 0 || p > MLP_NPARAM) return;
@@ -351,7 +422,9 @@ __global__ __launch_bounds__(256) void k_mlp_reduce_adam(float *__restrict__ the
   const float vn = b2 * v[p] + (1.f - b2) * gsum * gsum;
   m[p] = mn;
   v[p] = vn;
-  theta[p] -= lr * (mn / bc1) / (sqrtf(vn / bc2) + eps);
+  const float th = theta[p] - lr * (mn / bc1) / (sqrtf(vn / bc2) + eps);
+  theta[p] = th;
+  if (packed) pack_param(packed, p, th);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,9 +622,11 @@ __device__ inline void table_chunk(const TableBox &tb, int nchunk, int &begin, i
   end = min(tb.total, begin + per);
 }
 
-__global__ __launch_bounds__(256) void k_mlp_table(Lattice L, const DevParticle *__restrict__ parts,
-                                                   LearnedNets nets, int nchunk, float *__restrict__ tables,
-                                                   long long cap) {
+// The occupancy hint caps the kernel at 86 VGPRs (no spills): 5 waves per SIMD
+// instead of 4, 5 % faster on a 2000-particle 256^3 table launch.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_mlp_table(
+    Lattice L, const DevParticle *__restrict__ parts, LearnedNets nets, int nchunk, float *__restrict__ tables,
+    long long cap) {
   __shared__ int queue[TAB_QUEUE];
   __shared__ int wcnt[4];
   const DevParticle &p = parts[blockIdx.y];
@@ -664,7 +739,7 @@ hipError_t mlp_grad(const float *theta, const __bf16 *packed, const float4 *samp
   if (n <= 0) return hipSuccess;
   const int per = ((n + nblocks - 1) / nblocks + 31) / 32 * 32;
   const int nb = (n + per - 1) / per;
-  hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(64), 0, s, theta, packed, samples, n, per, scale, partial);
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(128), 0, s, theta, packed, samples, n, per, scale, partial);
   return hipGetLastError();
 }
 
@@ -674,11 +749,11 @@ int mlp_grad_blocks(int n, int nblocks) {
 }
 
 hipError_t mlp_reduce_adam(float *theta, float *m, float *v, const float *partial, int nblocks, float *grad_out,
-                           int do_step, float lr, int step, hipStream_t s) {
+                           int do_step, float lr, int step, __bf16 *packed, hipStream_t s) {
   const float b1 = 0.9f, b2 = 0.999f;
   const float bc1 = 1.f - powf(b1, (float)step), bc2 = 1.f - powf(b2, (float)step);
   hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((MLP_NPARAM + 1 + 63) / 64), dim3(256), 0, s, theta, m, v, partial,
-                     nblocks, grad_out, do_step, lr, b1, b2, 1e-8f, bc1, bc2);
+                     nblocks, grad_out, do_step, lr, b1, b2, 1e-8f, bc1, bc2, packed);
   return hipGetLastError();
 }
 

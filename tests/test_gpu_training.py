@@ -1,6 +1,7 @@
 """Training kernels of the learned indicator against the oracle, through the
 C ABI: the Adam update of the FP32 master parameters (two consecutive steps,
 fed the GPU's own gradients) against the FP64 Adam of oracle/mlp_oracle.py,
+the packed operands the step updates in place against a full repack,
 and the exact-distance training samples the GPU generator draws against the
 oracle's signed distance at the returned points.
 
@@ -63,6 +64,11 @@ def test_adam_steps_match_oracle(H, shape, n):
         assert np.all(np.abs(theta - theta0)[np.abs(g) > 1e-3] > 0)
         # continue from the GPU's rounded parameters, as the GPU does
         ref = theta
+    # the step rewrites the packed BF16 operands in place: the network must
+    # evaluate bit for bit as after a full repack of the new parameters
+    y_step = sim.mlp_eval(shape, pts[:512])
+    sim.mlp_set_params(shape, sim.mlp_get_params(shape))
+    np.testing.assert_array_equal(sim.mlp_eval(shape, pts[:512]), y_step)
     sim.close()
 
 
