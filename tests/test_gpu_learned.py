@@ -56,10 +56,12 @@ def test_forward_matches_oracle(H, seed):
     sim.close()
 
 
-@pytest.mark.parametrize("seed,n", [(0, 4096), (1, 1000), (2, 77)])
+@pytest.mark.parametrize("seed,n", [(0, 4096), (1, 1000), (2, 77), (3, 20000)])
 def test_gradient_matches_oracle(H, seed, n):
     """Batch sizes that fill, and do not fill, the 32-sample pairs and the
-    gradient workgroups."""
+    gradient workgroups; 20 000 samples give each workgroup two pairs (the
+    two wavefronts' per-lane sums then span several tiles) and a last
+    workgroup with one."""
     _log(f"gpu: mlp gradient seed {seed} n {n}")
     sim = _sim(H)
     theta = W.mlp_init_params(seed + 3)
