@@ -219,9 +219,14 @@ int hlbm_set_fluid_accel(hlbm_ctx *ctx, const double accel[3]);
  * to leading order in the penetration.  The force and torque act on the
  * state of the step's momentum exchange and are added to the hydrodynamic
  * ones in the equations of motion (hlbm_get_forces still reports the
- * hydrodynamic force and torque alone).  All n^2 pairs are tested every step.
- * Stream-ordered like hlbm_set_fluid_accel; range = 0 or both stiffnesses 0
- * turn it off.  HLBM_EINVAL for negative or non-finite values. */
+ * hydrodynamic force and torque alone).  Pairs are found by testing all
+ * n^2 pairs below 4096 particles and on a grid of the particle centres from
+ * there on; a particle may have at most 64 partners whose bounding spheres
+ * come within the range (64 non-spherical pairs below 4096 particles), and a
+ * step with more fails with HLBM_EUNSUPPORTED (checked when the step's
+ * results are read).  Stream-ordered like hlbm_set_fluid_accel; range = 0 or
+ * both stiffnesses 0 turn it off.  HLBM_EINVAL for negative or non-finite
+ * values. */
 int hlbm_set_contact(hlbm_ctx *ctx, double range, double stiffness, double wall_stiffness);
 
 /* Copy to host the hydrodynamic force F[n][3] and torque T[n][3] on each

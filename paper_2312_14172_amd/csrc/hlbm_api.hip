@@ -51,6 +51,7 @@ size_t pop_bytes(int precision) { return precision == HLBM_FP64 ? 8 : (precision
 struct Layout {
   size_t fA, fB, parts, order, stage_parts, tcnt[2], tlist[2], partial, contact, status, stage, total;
   size_t cshapes, cdirs, ccand, ccnt;  // node contact: records, node directions, partner lists and counts
+  size_t gcount, gfill, gcell, glist, gpos;  // contact pair search (grid of centres)
   // learned indicator (cfg.learned)
   size_t theta[NFAM], mom1[NFAM], mom2[NFAM], packed[NFAM], gpart, gout, pool, epts, eout, tables, mesh;
   size_t band[NFAM];  // band grids (learned or mesh shapes)
@@ -128,7 +129,12 @@ Layout make_layout(const hlbm_config *c, const Lattice &L) {
     y.tlist[b] = off; off += align_up((size_t)L.ntiles * MAXC * sizeof(int));
   }
   y.partial = off; off += align_up(np * LMAX_CAP * 6 * sizeof(double));
-  y.contact = off; off += align_up(np * (size_t)contact_chunks((int)np) * 3 * sizeof(double));
+  y.contact = off; off += align_up(np * (size_t)CONTACT_MAX_CHUNKS * 3 * sizeof(double));
+  y.gcount = off; off += align_up((size_t)(CGRID_MAX + 1) * sizeof(int));
+  y.gfill = off; off += align_up((size_t)CGRID_MAX * sizeof(int));
+  y.gcell = off; off += align_up(np * sizeof(int));
+  y.glist = off; off += align_up(np * sizeof(int));
+  y.gpos = off; off += align_up(np * sizeof(double4));
   y.cshapes = off; off += align_up(np * 6 * sizeof(double));
   y.cdirs = off; off += align_up((size_t)CONTACT_NODES * 3 * sizeof(double));
   y.ccand = off; off += align_up(np * CONTACT_CAND * sizeof(int));
@@ -187,6 +193,8 @@ struct hlbm_ctx {
   double *cshapes;    // contact force and torque of pairs with a non-spherical particle [n][6]
   double *cdirs;      // surface-node directions of that contact [CONTACT_NODES][3]
   int *ccand, *ccnt;  // its partner lists [n][CONTACT_CAND] and counts (zero between steps)
+  ContactWork cwork;  // pair-search arrays
+  double cwmax;       // largest sphere radius / circumradius of the particles
   bool nonspherical;  // the current particles include non-spherical ones
   ContactParams cparams;
   int lmax;           // z-layers of the largest momentum-exchange box
@@ -330,6 +338,9 @@ int hlbm_init(const hlbm_config *cfg, void *d_workspace, size_t bytes, hlbm_ctx 
   c->cdirs = (double *)(c->base + lay.cdirs);
   c->ccand = (int *)(c->base + lay.ccand);
   c->ccnt = (int *)(c->base + lay.ccnt);
+  c->cwork = ContactWork{(int *)(c->base + lay.gcount), (int *)(c->base + lay.gfill), (int *)(c->base + lay.gcell),
+                         (int *)(c->base + lay.glist), (double4 *)(c->base + lay.gpos)};
+  c->cwmax = 0.0;
   c->nonspherical = false;
   c->cparams = ContactParams{0.0, 0.0, 0.0, 0};
   c->lmax = 1;
@@ -449,6 +460,7 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
   if (n > 0 && !host) return fail(HLBM_EINVAL, "particles is NULL");
   const int nn[3] = {ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.nz};
   int cap = 1, lmax = 1;
+  double wmax = 0.0;
   for (int i = 0; i < n; ++i) {
     const hlbm_particle &p = host[i];
     const double *vals[] = {p.pos, p.quat, p.vel, p.omega, p.inertia, p.param};
@@ -482,6 +494,7 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
       if (!(p.param[0] > 0)) return fail(HLBM_EINVAL, "particle %d: mesh scale must be > 0", i);
       rc = p.param[0] * ctx->mesh_rc;
     }
+    wmax = std::max(wmax, rc);
     const double reach = rc + fmax(0.5 * ctx->cfg.eps, sqrt(2.0)) + 1.0;
     for (int k = 0; k < 3; ++k) {
       if (ctx->cfg.bc[k] == HLBM_BC_PERIODIC && 2.0 * reach >= nn[k])
@@ -563,6 +576,7 @@ int hlbm_set_particles(hlbm_ctx *ctx, int32_t n, const hlbm_particle *host) {
   ctx->mea_chunked = chunked ? 1 : 0;
   ctx->bin_cap = cap;
   ctx->lmax = lmax;
+  ctx->cwmax = wmax;
   int rc = rebin(ctx);
   if (rc) return rc;
   rc = mark_learned(ctx);
@@ -604,8 +618,18 @@ int hlbm_step(hlbm_ctx *ctx, int32_t nsteps) {
       const int layers = ctx->n >= 1000 ? 4 : 2;
       HIP_TRY(launch_mea(prec, ctx->L, ctx->fA, ctx->parts, ctx->order, ctx->n, ctx->lmax, layers, ctx->mea_chunked,
                          ctx->partial, s));
-      HIP_TRY(launch_contact(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->contact, ctx->ccand, ctx->ccnt,
-                             ctx->status, s));
+      if (ctx->cparams.on) {
+        // grid cells at least the largest pair reach 2 w_max + range wide
+        ContactGrid cg;
+        const double reach = 2.0 * ctx->cwmax + ctx->cparams.range;
+        const int nn[3] = {ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.nz};
+        for (int a = 0; a < 3; ++a) {
+          cg.g[a] = std::max(1, std::min(CGRID_AXIS, (int)floor(nn[a] / reach)));
+          cg.size[a] = (double)nn[a] / cg.g[a];
+        }
+        HIP_TRY(launch_contact(ctx->L, ctx->parts, ctx->n, ctx->cparams, cg, ctx->cwork, ctx->contact, ctx->ccand,
+                               ctx->ccnt, ctx->status, s));
+      }
       const bool shapes = ctx->cparams.on && ctx->nonspherical;
       if (shapes)
         HIP_TRY(launch_contact_shapes(ctx->L, ctx->parts, ctx->n, ctx->cparams, ctx->cdirs, ctx->ccand, ctx->ccnt,

@@ -37,20 +37,40 @@ struct ContactParams {
   double range, k, kw;
   int on;
 };
+constexpr int CONTACT_NODES = 1024;
+constexpr int CONTACT_CAND = 64;  // partners of one particle within the bounding-sphere range
+// pair search: n^2 tests in partner chunks below CONTACT_GRID_MIN particles,
+// a grid of the centres from there on
+constexpr int CONTACT_GRID_MIN = 4096;
 constexpr int CONTACT_TILE = 1024;      // partners staged in LDS at a time
 constexpr int CONTACT_MAX_CHUNKS = 64;  // partner chunks = partial sums per particle
+// contact records per particle: one per partner chunk, or one with the grid
 __host__ __device__ inline int contact_chunks(int n) {
-  return n < 1 ? 1 : (n > CONTACT_MAX_CHUNKS ? CONTACT_MAX_CHUNKS : n);
+  return n >= CONTACT_GRID_MIN ? 1 : (n < 1 ? 1 : (n > CONTACT_MAX_CHUNKS ? CONTACT_MAX_CHUNKS : n));
 }
-// per-chunk contact forces out[chunk][n][3] from the state before the EoM
-// cand / ccnt: partner lists of pairs with a non-spherical particle (appended)
-hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c, double *out,
-                          int *cand, int *ccnt, int *status, hipStream_t s);
+// uniform grid of particle centres for the contact pair search: g[a] cells of
+// size[a] >= the largest pair reach on axis a, at most CGRID_AXIS per axis
+constexpr int CGRID_AXIS = 32;
+constexpr int CGRID_MAX = CGRID_AXIS * CGRID_AXIS * CGRID_AXIS;
+struct ContactGrid {
+  int g[3];
+  double size[3];
+};
+// device work arrays of the pair search: gcount[CGRID_MAX + 1] (cell starts),
+// gfill[CGRID_MAX], gcell[n], glist[n], gpos[n] (centre and w = R or -R_circ)
+struct ContactWork {
+  int *gcount, *gfill, *gcell, *glist;
+  double4 *gpos;
+};
+// sphere-pair contact forces out[contact_chunks(n)][n][3] from the state
+// before the EoM, and the partner lists cand / ccnt of pairs with a
+// non-spherical particle (appended: ccnt must be zero on entry)
+hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c,
+                          const ContactGrid &cg, const ContactWork &w, double *out, int *cand, int *ccnt, int *status,
+                          hipStream_t s);
 // contact of pairs with a non-spherical particle and of such particles with
 // walls: out[p] = (F, T); dirs = CONTACT_NODES unit directions (x, y, z);
 // cand / ccnt: the partner lists k_contact fills (emptied here)
-constexpr int CONTACT_NODES = 1024;
-constexpr int CONTACT_CAND = 64;  // partners of one particle in the node contact
 hipError_t launch_contact_shapes(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c,
                                  const double *dirs, int *cand, int *ccnt, double *out, hipStream_t s);
 // shapes: the records of launch_contact_shapes, or NULL

@@ -11,8 +11,12 @@
 //              order, gravity and buoyancy, Newton-Euler and quaternion update
 //              in FP64, then the particle appended to the tile lists of its new
 //              coupling box (tiles of 64 x 4 x 4 cells);
-//   k_contact  (only with contact set) pairwise sphere repulsion, launched
-//              between the two and summed into the force by k_eom_bin.
+//   k_cgrid_*, k_contact, k_contact_shapes  (only with contact set) the
+//              contact pair search on a grid of the centres and the
+//              repulsion forces, launched between the two and added to the
+//              force by k_eom_bin.
+#include <climits>
+
 #include "hlbm_device.h"
 #include "hlbm_internal.h"
 
@@ -459,18 +463,220 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST::kind ==
 // cites one, Sec. 2.2, 3.2 and 5.3): the short-range repulsion of Glowinski et al.
 // (J. Comput. Phys. 169, 2001).  Spheres p and q with centre distance
 // d < R_p + R_q + range (minimum image on periodic axes) repel along the line
-// of centres with k ((R_p + R_q + range - d) / range)^2.  Workgroup (bp, c)
-// takes 256 particles p and the c-th of up to 64 contiguous chunks of
-// partners q (enough workgroups to fill the chip for a few hundred
-// particles), staged in LDS 1024 at a time as (X, w) with w = R for spheres
-// and -R_circ for other shapes; each thread sums its chunk in increasing q
-// into out[c][p].  Pairs with a non-spherical particle whose bounding
-// spheres come within the range are appended to p's candidate list
-// (cand[p][0 .. CONTACT_CAND), count ccnt[p]) for k_contact_shapes, in no
-// fixed order (that kernel sorts them).  O(n^2) pair tests without a
-// neighbour structure; a pair out of range costs a squared distance and one
-// compare.
-__global__ __launch_bounds__(256) void k_contact(Lattice L, const DevParticle *__restrict__ parts, int n,
+// of centres with k ((R_p + R_q + range - d) / range)^2.
+//
+// Pair search on a uniform grid of the particle centres (from
+// CONTACT_GRID_MIN particles on; below, k_contact_pairs): cells at least the
+// largest pair reach 2 w_max + range wide on every axis (w = R for spheres,
+// the circumradius otherwise), so the partners of p lie in the 27 cells
+// around p's cell (fewer where an axis has one or two cells; no wrap across
+// walls).  The grid is a counting sort: k_cgrid_count counts the centres per
+// cell (and stores each centre with w), k_cgrid_scan turns the counts into
+// cell starts, k_cgrid_fill places the particle indices (in no fixed order
+// within a cell).  k_contact then lists, per particle, the partners whose
+// bounding spheres come within the range (at most CONTACT_CAND; more is
+// reported as ST_CONTACT_OVERFLOW), ranks them by index, sums the sphere
+// pairs' forces into out[p] and copies the pairs with a non-spherical
+// particle into cand[p] / ccnt[p] for k_contact_shapes.  The sums and lists
+// are independent of the order within the cells.
+__device__ inline int cgrid_axis(double x, double size, int g) {
+  double q = x / size;
+  if (!(q >= 0.0)) q = 0.0;  // also a non-finite centre
+  if (q > (double)(g - 1)) q = (double)(g - 1);
+  return (int)q;
+}
+
+__global__ __launch_bounds__(256) void k_cgrid_count(const DevParticle *__restrict__ parts, int n, ContactGrid cg,
+                                                     int *__restrict__ gcount, int *__restrict__ gcell,
+                                                     double4 *__restrict__ gpos) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const DevParticle &P = parts[p];
+  const double *X = P.X;
+  const int cell = cgrid_axis(X[0], cg.size[0], cg.g[0]) +
+                   cg.g[0] * (cgrid_axis(X[1], cg.size[1], cg.g[1]) + cg.g[1] * cgrid_axis(X[2], cg.size[2], cg.g[2]));
+  gcell[p] = cell;
+  // centre and w = R for spheres, -circumradius otherwise
+  gpos[p] = make_double4(X[0], X[1], X[2], P.shape == 0 ? P.prm[0] : -P.rc);
+  atomicAdd(&gcount[cell], 1);
+}
+
+// One 1024-thread workgroup: gcount[0 .. ncells) -> exclusive starts in
+// gcount (gcount[ncells] = n) and the same starts in gfill (the insertion
+// pointers of k_cgrid_fill).
+__global__ __launch_bounds__(1024) void k_cgrid_scan(int *__restrict__ gcount, int ncells,
+                                                     int *__restrict__ gfill) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (ncells + 1023) / 1024;
+  const int b = min(ncells, t * per), e = min(ncells, b + per);
+  int sum = 0;
+  for (int c = b; c < e; ++c) sum += gcount[c];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - sum;  // exclusive prefix of this thread's range
+  for (int c = b; c < e; ++c) {
+    const int v = gcount[c];
+    gcount[c] = run;
+    gfill[c] = run;
+    run += v;
+  }
+  if (t == 1023) gcount[ncells] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_cgrid_fill(int n, const int *__restrict__ gcell, int *__restrict__ gfill,
+                                                    int *__restrict__ glist) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  glist[atomicAdd(&gfill[gcell[p]], 1)] = p;
+}
+
+// distinct grid cells next to cell c on an axis of g cells (wrapped on a
+// periodic axis, clipped at walls); returns their count
+__device__ inline int cgrid_near(int c, int g, bool periodic, int *out) {
+  if (g <= 2 && periodic) {
+    for (int k = 0; k < g; ++k) out[k] = k;
+    return g;
+  }
+  int m = 0;
+  for (int d = -1; d <= 1; ++d) {
+    int v = c + d;
+    if (periodic) v = v < 0 ? v + g : (v >= g ? v - g : v);
+    else if (v < 0 || v >= g) continue;
+    out[m++] = v;
+  }
+  return m;
+}
+
+// One wavefront per particle p (four per workgroup): the members of the
+// cells around p's cell are enumerated as one flat list spread over the
+// lanes, the partners within the range compacted in LDS, ranked by index,
+// and then summed (sphere pairs, fixed wavefront tree) or copied to
+// cand[p] in increasing index (pairs with a non-spherical particle).
+__global__ __launch_bounds__(256) void k_contact(Lattice L, int n, ContactParams c, ContactGrid cg,
+                                                 const double4 *__restrict__ gpos, const int *__restrict__ gstart,
+                                                 const int *__restrict__ gcell, const int *__restrict__ glist,
+                                                 double *__restrict__ out, int *__restrict__ cand,
+                                                 int *__restrict__ ccnt, int *status) {
+  __shared__ int cbeg[4][28], cpre[4][28];
+  __shared__ int found[4][CONTACT_CAND], sorted[4][CONTACT_CAND];
+  const int w = wave_id(), lane = lane_id();
+  const int p = blockIdx.x * 4 + w;
+  if (p >= n) return;  // uniform per wavefront; no workgroup barrier below
+  const int nn[3] = {L.nx, L.ny, L.nz};
+  const double4 P = gpos[p];
+  const int cell = gcell[p];
+  const int cc[3] = {cell % cg.g[0], (cell / cg.g[0]) % cg.g[1], cell / (cg.g[0] * cg.g[1])};
+  int near[3][3], nnear[3];
+  for (int a = 0; a < 3; ++a) nnear[a] = cgrid_near(cc[a], cg.g[a], !L.bc[a], near[a]);
+  const int ncell = nnear[0] * nnear[1] * nnear[2];
+  // members of the neighbouring cells: counts, then their running offsets
+  int cnt_c = 0, beg_c = 0;
+  if (lane < ncell) {
+    const int ix = lane % nnear[0], iy = (lane / nnear[0]) % nnear[1], iz = lane / (nnear[0] * nnear[1]);
+    const int q_cell = near[0][ix] + cg.g[0] * (near[1][iy] + cg.g[1] * near[2][iz]);
+    beg_c = gstart[q_cell];
+    cnt_c = gstart[q_cell + 1] - beg_c;
+  }
+  int pre = cnt_c;  // inclusive prefix over the lanes
+  for (int off = 1; off < 32; off <<= 1) {
+    const int v = __shfl_up(pre, off, 64);
+    if (lane >= off) pre += v;
+  }
+  const int total = __shfl(pre, 31, 64);
+  if (lane < 28) {
+    cbeg[w][lane] = beg_c;
+    cpre[w][lane] = pre - cnt_c;
+  }
+  __builtin_amdgcn_wave_barrier();
+  int nfound = 0;
+  bool over = false;
+  for (int i0 = 0; i0 < total; i0 += 64) {
+    const int i = i0 + lane;
+    bool in = false;
+    int q = 0;
+    if (i < total) {
+      int j = 0;
+      while (j + 1 < ncell && cpre[w][j + 1] <= i) ++j;
+      q = glist[cbeg[w][j] + (i - cpre[w][j])];
+      if (q != p) {
+        const double4 Q = gpos[q];
+        const double Qx[3] = {Q.x, Q.y, Q.z}, Px[3] = {P.x, P.y, P.z};
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          double dx = Px[a] - Qx[a];
+          if (!L.bc[a]) dx = dx > 0.5 * nn[a] ? dx - nn[a] : (dx < -0.5 * nn[a] ? dx + nn[a] : dx);
+          d2 += dx * dx;
+        }
+        const double reach = fabs(P.w) + fabs(Q.w) + c.range;
+        in = d2 < reach * reach && d2 != 0.0;
+      }
+    }
+    const unsigned long long mask = __ballot(in);
+    const int slot = nfound + __popcll(mask & ((1ull << lane) - 1ull));
+    if (in) {
+      if (slot < CONTACT_CAND) found[w][slot] = q;
+      else over = true;
+    }
+    nfound += __popcll(mask);
+  }
+  if (__ballot(over)) {
+    if (lane == 0) atomicOr(status, ST_CONTACT_OVERFLOW);
+  }
+  const int np = min(nfound, CONTACT_CAND);
+  __builtin_amdgcn_wave_barrier();
+  // rank by index
+  if (lane < np) {
+    const int v = found[w][lane];
+    int rank = 0;
+    for (int k = 0; k < np; ++k) rank += found[w][k] < v;
+    sorted[w][rank] = v;
+  }
+  __builtin_amdgcn_wave_barrier();
+  double f[3] = {0.0, 0.0, 0.0};
+  bool shape_pair = false;
+  int q = -1;
+  if (lane < np) {
+    q = sorted[w][lane];
+    const double4 Q = gpos[q];
+    if (P.w > 0.0 && Q.w > 0.0) {
+      const double Qx[3] = {Q.x, Q.y, Q.z}, Px[3] = {P.x, P.y, P.z};
+      double dx[3];
+      for (int a = 0; a < 3; ++a) {
+        dx[a] = Px[a] - Qx[a];
+        if (!L.bc[a]) dx[a] = dx[a] > 0.5 * nn[a] ? dx[a] - nn[a] : (dx[a] < -0.5 * nn[a] ? dx[a] + nn[a] : dx[a]);
+      }
+      const double d = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+      const double sc = (P.w + Q.w + c.range - d) / c.range;
+      for (int a = 0; a < 3; ++a) f[a] = c.k * sc * sc * dx[a] / d;
+    } else {
+      shape_pair = c.k != 0.0;
+    }
+  }
+  const unsigned long long smask = __ballot(shape_pair);
+  if (shape_pair) cand[(size_t)p * CONTACT_CAND + __popcll(smask & ((1ull << lane) - 1ull))] = q;
+  for (int a = 0; a < 3; ++a) f[a] = wave_sum(f[a]);
+  if (lane == 0) {
+    ccnt[p] = __popcll(smask);
+    for (int a = 0; a < 3; ++a) out[(size_t)p * 3 + a] = f[a];
+  }
+}
+
+// Pair search without a grid, for fewer than CONTACT_GRID_MIN particles
+// (where the grid's extra launches and dependent loads cost more than the
+// n^2 tests): workgroup (bp, c) takes 256 particles p and the c-th of up to
+// 64 contiguous chunks of partners q (enough workgroups to fill the chip for
+// a few hundred particles), staged in LDS 1024 at a time as (X, w); each
+// thread sums its chunk in increasing q into out[c][p].  Pairs with a
+// non-spherical particle are appended to cand[p] / ccnt[p] in no fixed order
+// (k_contact_shapes sorts them).
+__global__ __launch_bounds__(256) void k_contact_pairs(Lattice L, const DevParticle *__restrict__ parts, int n,
                                                  ContactParams c, double *__restrict__ out, int *__restrict__ cand,
                                                  int *__restrict__ ccnt, int *status) {
   __shared__ double4 sq[CONTACT_TILE];
@@ -564,7 +770,9 @@ __global__ __launch_bounds__(64) void k_eom_bin(Lattice L, DevParticle *__restri
   const bool have = t < nmax;
   if (have)
     for (int k = 0; k < 6; ++k) first[k] = src[t * 6 + k];
-  // contact: lane b holds chunk b's sum, reduced by the fixed wavefront tree
+  // contact: lane b holds record b of the particle (contact_chunks(n) of
+  // them below CONTACT_GRID_MIN particles, else one), reduced by the fixed
+  // wavefront tree
   double fc[3] = {0.0, 0.0, 0.0};
   if (CONTACT && t < contact_chunks(n))
     for (int a = 0; a < 3; ++a) fc[a] = contact[((size_t)t * n + pid) * 3 + a];
@@ -987,11 +1195,25 @@ hipError_t launch_mea(int prec, const Lattice &L, const void *A, const DevPartic
   return hipGetLastError();
 }
 
-hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c, double *out,
-                          int *cand, int *ccnt, int *status, hipStream_t s) {
+hipError_t launch_contact(const Lattice &L, const DevParticle *parts, int n, const ContactParams &c,
+                          const ContactGrid &cg, const ContactWork &w, double *out, int *cand, int *ccnt, int *status,
+                          hipStream_t s) {
   if (n <= 0 || !c.on) return hipSuccess;
-  const dim3 grid(blocks_for(n, 256), contact_chunks(n));
-  hipLaunchKernelGGL(k_contact, grid, dim3(256), 0, s, L, parts, n, c, out, cand, ccnt, status);
+  if (n < CONTACT_GRID_MIN) {
+    const dim3 grid(blocks_for(n, 256), contact_chunks(n));
+    hipLaunchKernelGGL(k_contact_pairs, grid, dim3(256), 0, s, L, parts, n, c, out, cand, ccnt, status);
+    return hipGetLastError();
+  }
+  const int ncells = cg.g[0] * cg.g[1] * cg.g[2];
+  if (ncells < 1 || ncells > CGRID_MAX) return hipErrorInvalidValue;
+  hipError_t e = launch_fill_int(w.gcount, 0, ncells + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cgrid_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, parts, n, cg, w.gcount, w.gcell,
+                     w.gpos);
+  hipLaunchKernelGGL(k_cgrid_scan, dim3(1), dim3(1024), 0, s, w.gcount, ncells, w.gfill);
+  hipLaunchKernelGGL(k_cgrid_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.gcell, w.gfill, w.glist);
+  hipLaunchKernelGGL(k_contact, dim3(blocks_for(n, 4)), dim3(256), 0, s, L, n, c, cg, w.gpos, w.gcount, w.gcell,
+                     w.glist, out, cand, ccnt, status);
   return hipGetLastError();
 }
 

@@ -168,6 +168,52 @@ def test_many_spheres_contact_chunks_fp64(H, oracle_mod):
     np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-10 * np.max(np.abs(Fo)))
 
 
+def test_contact_grid_many_particles_fp64(H, oracle_mod):
+    """From 4096 particles on, the pair search runs on a grid of the centres
+    (the 27 cells around each particle, wrapped on the periodic axes, not
+    across the walls).  4488 small moving spheres and 12 spheroids, placed at
+    random (some overlapping), on 96 x 96 x 64 with walls in z; 3 FP64 steps
+    against the oracle's all-pairs contact, sphere pairs by the closed form
+    and pairs with a spheroid by the node model."""
+    n, bc = (96, 96, 64), (0, 0, 1)
+    rng = np.random.default_rng(12)
+    count = 4500
+    pos = rng.uniform((0.0, 0.0, 2.5), (96.0, 96.0, 61.5), (count, 3))
+    vel = rng.uniform(-2e-3, 2e-3, (count, 3))
+    sph = W.equal_volume_params(W.SPHEROID, 1.0)
+    recs = []
+    for i, (p, v) in enumerate(zip(pos, vel)):
+        if i % 375 == 0:
+            recs.append(W.make_particle(W.SPHEROID, sph, tuple(p), quat=W.shoemake_quaternion(rng), vel=tuple(v)))
+        else:
+            recs.append(W.make_particle(W.SPHERE, (1.0,), tuple(p), vel=tuple(v)))
+    parts = np.array(recs)
+    contact = (0.8, 2e-3, 1e-3)
+    g = (0.0, 0.0, -1e-5)
+    _log(f"gpu: contact grid, {count} particles, 3 steps FP64")
+    sim = H.Simulation(n, bc, 0.8, "fp64", max_particles=count, gravity=g)
+    sim.set_particles(parts)
+    sim.set_contact(*contact)
+    sim.step(1)
+    sim.step(2)
+    F, _, st = sim.get_forces()
+    sim.close()
+    orc = oracle_mod.Oracle(n, bc, 0.8, gravity=g, contact=contact)
+    P = orc.to_parts(parts)
+    Fc0, _ = orc.contact_forces(P, torque=True)
+    touching = int(np.count_nonzero(np.abs(Fc0).sum(1)))
+    shapes = np.flatnonzero(parts["shape"] != W.SPHERE)
+    shape_touch = int(np.count_nonzero(np.abs(Fc0[shapes]).sum(1)))
+    Fo, _ = orc.run(P, orc.equilibrium(), 3)
+    _log(f"  {touching} of {count} in contact range ({shape_touch} spheroids); "
+         f"max |dU| {np.abs(st['vel'] - P['U']).max():.3e}, |dW| {np.abs(st['omega'] - P['W']).max():.3e}")
+    assert touching > 300 and shape_touch >= 3
+    np.testing.assert_allclose(st["vel"], P["U"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(st["omega"], P["W"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(st["pos"], P["X"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-10 * np.max(np.abs(Fo)))
+
+
 def _shape_cluster():
     """Rounded cubes, spheroids, a mesh particle and spheres in contact with
     each other (one pair across the periodic x boundary) and with the bottom
