@@ -214,6 +214,41 @@ def test_contact_grid_many_particles_fp64(H, oracle_mod):
     np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-10 * np.max(np.abs(Fo)))
 
 
+def test_contact_grid_small_axis_and_cap_fp64(H, oracle_mod):
+    """The grid search's edge cases: a periodic axis of two cells (both
+    visited once, not the same cell twice), an axis whose cell count is
+    capped at 32 (cells wider than the reach), walls in y.  4200 spheres of
+    radius 0.6 with a contact range of 2.3 on 512 x 104 x 8 (sparse enough
+    for the 48-particle tile lists); 3 FP64 steps against the oracle."""
+    n, bc = (512, 104, 8), (0, 1, 0)
+    rng = np.random.default_rng(13)
+    count = 4200
+    pos = rng.uniform((0.0, 1.0, 0.0), (512.0, 103.0, 8.0), (count, 3))
+    vel = rng.uniform(-2e-3, 2e-3, (count, 3))
+    parts = np.array([W.make_particle(W.SPHERE, (0.6,), tuple(p), vel=tuple(v)) for p, v in zip(pos, vel)])
+    contact = (2.3, 1e-3, 1e-3)
+    reach = 2 * 0.6 + contact[0]
+    cells = [min(32, int(np.floor(n[a] / reach))) for a in range(3)]
+    assert cells == [32, 29, 2]
+    g = (0.0, -1e-5, 0.0)
+    _log(f"gpu: contact grid edge cases, {count} spheres, cells {cells}, 3 steps FP64")
+    sim = H.Simulation(n, bc, 0.8, "fp64", max_particles=count, gravity=g)
+    sim.set_particles(parts)
+    sim.set_contact(*contact)
+    sim.step(3)
+    F, _, st = sim.get_forces()
+    sim.close()
+    orc = oracle_mod.Oracle(n, bc, 0.8, gravity=g, contact=contact)
+    P = orc.to_parts(parts)
+    touching = int(np.count_nonzero(np.abs(orc.contact_forces(P)).sum(1)))
+    Fo, _ = orc.run(P, orc.equilibrium(), 3)
+    _log(f"  {touching} of {count} in contact range; max |dU| {np.abs(st['vel'] - P['U']).max():.3e}")
+    assert touching > 2000
+    np.testing.assert_allclose(st["vel"], P["U"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(st["pos"], P["X"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-10 * np.max(np.abs(Fo)))
+
+
 def _shape_cluster():
     """Rounded cubes, spheroids, a mesh particle and spheres in contact with
     each other (one pair across the periodic x boundary) and with the bottom
