@@ -851,10 +851,96 @@ __device__ inline double body_sdf(const Lattice &L, const DevParticle &P, const 
   return sdf_body<double>(P.shape, P.prm[0], P.prm[1], y[0], y[1], y[2]);
 }
 
-// normalised central-difference gradient (step 1e-5) of the body-frame
-// signed distance
+// Nearest point (x0, x1) to (y0, y1) >= 0 on the ellipse (u/e0)^2 + (v/e1)^2
+// = 1, e0 >= e1: the same monotone Newton iteration for the Lagrange root t
+// as the distance function of the coupling, returning the point.
+__device__ inline void ellipse_nearest(double e0, double e1, double y0, double y1, double &x0, double &x1) {
+  const double e0s = e0 * e0, e1s = e1 * e1;
+  if (y1 > 0.0) {
+    if (y0 > 0.0) {
+      const double a = e0 * y0, b = e1 * y1, lo = b - e1s;
+      double t = 0.0;
+      for (int it = 0; it < 100; ++it) {
+        const double i0 = 1.0 / (t + e0s), i1 = 1.0 / (t + e1s);
+        const double r0 = a * i0, r1 = b * i1;
+        const double gv = r0 * r0 + r1 * r1 - 1.0;
+        const double dg = -2.0 * (r0 * r0 * i0 + r1 * r1 * i1);
+        double tn = t - gv / dg;
+        if (tn < lo) tn = lo;
+        if (it > 0 && !(tn > t)) break;
+        t = tn;
+      }
+      x0 = e0s * y0 / (t + e0s);
+      x1 = e1s * y1 / (t + e1s);
+    } else {
+      x0 = 0.0;
+      x1 = e1;
+    }
+    return;
+  }
+  const double den = e0s - e1s;
+  if (e0 * y0 < den) {
+    x0 = e0s * y0 / den;
+    const double s = x0 / e0;
+    x1 = e1 * sqrt(fmax(0.0, 1.0 - s * s));
+  } else {
+    x0 = e0;
+    x1 = 0.0;
+  }
+}
+
+// Unit gradient of the body-frame signed distance at y: the outward normal
+// at the nearest surface point.  Closed forms for the sphere, the rounded
+// cube (the dilation direction outside the core, the axis of the nearest face
+// inside it) and the spheroid (the ellipse normal at the nearest point of the
+// meridian plane); central differences (step 1e-5) for a mesh.
 template <bool MESH>
 __device__ inline void body_sdf_normal(const Lattice &L, const DevParticle &P, const double *y, double *g) {
+  if (P.shape == 0) {
+    const double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    if (r > 0.0) {
+      for (int k = 0; k < 3; ++k) g[k] = y[k] / r;
+    } else {
+      g[0] = 1.0; g[1] = g[2] = 0.0;
+    }
+    return;
+  }
+  if (P.shape == 1) {
+    const double c = P.prm[0] - P.prm[1];
+    double q[3], o[3], on = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      q[k] = fabs(y[k]) - c;
+      o[k] = fmax(q[k], 0.0);
+      on += o[k] * o[k];
+    }
+    if (on > 0.0) {
+      on = 1.0 / sqrt(on);
+      for (int k = 0; k < 3; ++k) g[k] = copysign(o[k] * on, y[k]);
+    } else {
+      const int m = q[0] >= q[1] && q[0] >= q[2] ? 0 : (q[1] >= q[2] ? 1 : 2);
+      for (int k = 0; k < 3; ++k) g[k] = k == m ? copysign(1.0, y[k]) : 0.0;
+    }
+    return;
+  }
+  if (P.shape == 2) {
+    // symmetry axis body x (semi-axis a), radial semi-axis b
+    const double a = P.prm[0], b = P.prm[1];
+    const double y0 = fabs(y[0]), r = sqrt(y[1] * y[1] + y[2] * y[2]);
+    double x0, x1;
+    if (a >= b) ellipse_nearest(a, b, y0, r, x0, x1);
+    else ellipse_nearest(b, a, r, y0, x1, x0);
+    const double n0 = x0 / (a * a), n1 = x1 / (b * b);
+    const double nn = 1.0 / sqrt(n0 * n0 + n1 * n1);
+    g[0] = copysign(n0 * nn, y[0]);
+    if (r > 0.0) {
+      g[1] = n1 * nn * y[1] / r;
+      g[2] = n1 * nn * y[2] / r;
+    } else {  // on the axis: the nearest points form a ring; one of them
+      g[1] = n1 * nn;
+      g[2] = 0.0;
+    }
+    return;
+  }
   const double h = 1e-5;
   double dv[6];
 #pragma unroll 1

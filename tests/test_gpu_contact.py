@@ -174,7 +174,10 @@ def test_contact_grid_many_particles_fp64(H, oracle_mod):
     across the walls).  4488 small moving spheres and 12 spheroids, placed at
     random (some overlapping), on 96 x 96 x 64 with walls in z; 3 FP64 steps
     against the oracle's all-pairs contact, sphere pairs by the closed form
-    and pairs with a spheroid by the node model."""
+    and pairs with a spheroid by the node model.  The library takes the
+    partner's distance gradient in closed form, the oracle by central
+    differences (relative error ~1e-10), so velocities are held to 1e-8 of
+    the contact's velocity scale (3 steps of |F_c| / m at the start)."""
     n, bc = (96, 96, 64), (0, 0, 1)
     rng = np.random.default_rng(12)
     count = 4500
@@ -200,17 +203,19 @@ def test_contact_grid_many_particles_fp64(H, oracle_mod):
     sim.close()
     orc = oracle_mod.Oracle(n, bc, 0.8, gravity=g, contact=contact)
     P = orc.to_parts(parts)
-    Fc0, _ = orc.contact_forces(P, torque=True)
+    Fc0, Tc0 = orc.contact_forces(P, torque=True)
     touching = int(np.count_nonzero(np.abs(Fc0).sum(1)))
     shapes = np.flatnonzero(parts["shape"] != W.SPHERE)
+    du = 3 * np.max(np.linalg.norm(Fc0, axis=1) / parts["mass"])
+    dw = 3 * np.max(np.linalg.norm(Tc0, axis=1) / parts["inertia"].min(axis=1))
     shape_touch = int(np.count_nonzero(np.abs(Fc0[shapes]).sum(1)))
     Fo, _ = orc.run(P, orc.equilibrium(), 3)
     _log(f"  {touching} of {count} in contact range ({shape_touch} spheroids); "
          f"max |dU| {np.abs(st['vel'] - P['U']).max():.3e}, |dW| {np.abs(st['omega'] - P['W']).max():.3e}")
-    assert touching > 300 and shape_touch >= 3
-    np.testing.assert_allclose(st["vel"], P["U"], rtol=0, atol=1e-13)
-    np.testing.assert_allclose(st["omega"], P["W"], rtol=0, atol=1e-12)
-    np.testing.assert_allclose(st["pos"], P["X"], rtol=0, atol=1e-12)
+    assert touching > 300 and shape_touch >= 3 and du > 1e-3 and dw > 1e-3
+    np.testing.assert_allclose(st["vel"], P["U"], rtol=0, atol=1e-8 * du)
+    np.testing.assert_allclose(st["omega"], P["W"], rtol=0, atol=1e-8 * dw)
+    np.testing.assert_allclose(st["pos"], P["X"], rtol=0, atol=1e-11)
     np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-10 * np.max(np.abs(Fo)))
 
 
@@ -277,9 +282,10 @@ def test_shape_contact_matches_oracle_fp64(H, oracle_mod):
     (surface nodes against the partner's signed distance) through 6 FP64
     steps against the oracle.  The library places the nodes on the surface in
     closed form (or by the nearest triangle hit) with analytic normals for the
-    area weights; the oracle bisects the signed distance along the rays and
-    takes central-difference normals, so the two node sets agree to about
-    1e-10 relative, and so do the contact forces."""
+    area weights, and the partner's distance gradient in closed form (central
+    differences for the mesh); the oracle bisects the signed distance along
+    the rays and takes central-difference gradients, so the two agree to
+    about 1e-10 relative, and so do the contact forces."""
     n, bc = (40, 32, 36), (0, 0, 1)
     v, t = W.MESH_UNIT
     parts = _shape_cluster()
