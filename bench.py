@@ -109,7 +109,7 @@ def load_traffic(workload: str, precision: str):
     return int(rec["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in rec else None
 
 
-def errors_vs_fp64(H, wl, precision, steps, every, coupling="hlbm"):
+def errors_vs_fp64(H, wl, precision, steps, every, coupling="hlbm", contact=None):
     """This precision against the FP64 plain form (exact indicator) of the
     same workload from rest: velocity L2-relative and max |rho - rho_ref|
     after `steps`, the per-particle force averaged over samples every `every`
@@ -135,6 +135,8 @@ def errors_vs_fp64(H, wl, precision, steps, every, coupling="hlbm"):
             sim.set_particles(wl.particles)
         else:
             sim, _ = make_sim(H, W, wl, prec, coupling)
+        if contact:
+            sim.set_contact(*contact)
         acc = np.zeros((len(wl.particles), 3))
         vz = []
         for k in range(nsamp):
@@ -160,12 +162,13 @@ def errors_vs_fp64(H, wl, precision, steps, every, coupling="hlbm"):
                    f"{last * every} steps"}
 
 
-def cpu_baseline(wl, target_s=12.0):
+def cpu_baseline(wl, target_s=12.0, contact=None):
     """The FP64 oracle as it stands, on a bounded number of steps of the same
-    workload, all host cores (OpenMP): steps are timed one at a time until
-    about target_s seconds have passed (at least one, at most 200)."""
+    workload (with the same contact, if any), all host cores (OpenMP): steps
+    are timed one at a time until about target_s seconds have passed (at
+    least one, at most 200)."""
     from oracle import oracle as orc
-    o = orc.Oracle(wl.n, wl.bc, wl.tau, eps=wl.eps, rho_f=wl.rho_f, gravity=wl.gravity)
+    o = orc.Oracle(wl.n, wl.bc, wl.tau, eps=wl.eps, rho_f=wl.rho_f, gravity=wl.gravity, contact=contact)
     P = o.to_parts(wl.particles)
     f = o.equilibrium()
     steps, dt = 0, 0.0
@@ -202,6 +205,9 @@ def main():
                     help="exact-difference source (hlbm) or partially saturated collision (psm)")
     ap.add_argument("--check-steps", type=int, default=1000,
                     help="steps of the untimed runs compared with FP64")
+    ap.add_argument("--contact", type=float, nargs=3, default=None, metavar=("RANGE", "K", "KW"),
+                    help="turn on the contact repulsion (range in cells, pair and wall stiffness); the "
+                         "oracle's node contact is slow, so --no-cpu-baseline suits large workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-force-check", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -224,6 +230,8 @@ def main():
           f"phi={wl.solid_fraction:.3f}", file=sys.stderr, flush=True)
     H.lib()
     sim, train_reports = make_sim(H, W, wl, precision, args.coupling)
+    if args.contact:
+        sim.set_contact(*args.contact)
     sim.step(args.warmup)
     sim.get_forces()            # synchronises and reports kernel errors
     torch.cuda.synchronize()
@@ -269,11 +277,12 @@ def main():
     extra = {}
     if not args.no_force_check and precision != "fp64" and len(wl.particles):
         print(f"[bench] errors against FP64: {args.check_steps} steps per precision", file=sys.stderr, flush=True)
-        extra["errors_vs_fp64"] = errors_vs_fp64(H, wl, precision, args.check_steps, 10, args.coupling)
+        extra["errors_vs_fp64"] = errors_vs_fp64(H, wl, precision, args.check_steps, 10, args.coupling,
+                                                 args.contact)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl)
+        cpu = cpu_baseline(wl, contact=args.contact)
 
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
@@ -282,7 +291,8 @@ def main():
         "dtype": DTYPE[precision], "data": "synthetic",
         "config": {"workload": wl.name, "lattice": list(wl.n), "bc": list(wl.bc),
                    "particles": int(len(wl.particles)), "solid_fraction": round(wl.solid_fraction, 4),
-                   "tau": wl.tau, "storage": precision, "coupling": args.coupling, "parallelism": "single GPU"},
+                   "tau": wl.tau, "storage": precision, "coupling": args.coupling, "contact": args.contact,
+                   "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu,
         "segments": {"count": nseg, "steps_each": args.steps // nseg,
                      "ms_per_step": [round(v, 5) for v in seg_ms],
