@@ -11,8 +11,9 @@
 //              order, gravity and buoyancy, Newton-Euler and quaternion update
 //              in FP64, then the particle appended to the tile lists of its new
 //              coupling box (tiles of 64 x 4 x 4 cells);
-//   k_cgrid_*, k_contact, k_contact_shapes  (only with contact set) the
-//              contact pair search on a grid of the centres and the
+//   k_contact_pairs, or k_cgrid_* and k_contact, then k_contact_shapes
+//              (only with contact set): the contact pair search (all pairs,
+//              or a grid of the centres from 4096 particles on) and the
 //              repulsion forces, launched between the two and added to the
 //              force by k_eom_bin.
 #include <climits>
