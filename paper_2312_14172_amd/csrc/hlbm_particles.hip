@@ -853,8 +853,9 @@ __device__ inline double body_sdf(const Lattice &L, const DevParticle &P, const 
 }
 
 // Nearest point (x0, x1) to (y0, y1) >= 0 on the ellipse (u/e0)^2 + (v/e1)^2
-// = 1, e0 >= e1: the same monotone Newton iteration for the Lagrange root t
-// as the distance function of the coupling, returning the point.
+// = 1, e0 >= e1: the same monotone Newton iteration for the Lagrange root t,
+// with the same operations, as the distance function of the coupling, so
+// that |(x0, x1) - (y0, y1)| is that distance bit for bit.
 __device__ inline void ellipse_nearest(double e0, double e1, double y0, double y1, double &x0, double &x1) {
   const double e0s = e0 * e0, e1s = e1 * e1;
   if (y1 > 0.0) {
@@ -866,7 +867,7 @@ __device__ inline void ellipse_nearest(double e0, double e1, double y0, double y
         const double r0 = a * i0, r1 = b * i1;
         const double gv = r0 * r0 + r1 * r1 - 1.0;
         const double dg = -2.0 * (r0 * r0 * i0 + r1 * r1 * i1);
-        double tn = t - gv / dg;
+        double tn = t - gv * (1.0 / dg);
         if (tn < lo) tn = lo;
         if (it > 0 && !(tn > t)) break;
         t = tn;
@@ -888,6 +889,31 @@ __device__ inline void ellipse_nearest(double e0, double e1, double y0, double y
     x0 = e0;
     x1 = 0.0;
   }
+}
+
+// Signed distance of the spheroid (symmetry axis body x with semi-axis a,
+// radial semi-axis b) at the body-frame point y, and its unit gradient: the
+// ellipse normal at the nearest point of the meridian plane.  The distance
+// equals the coupling's spheroid distance bit for bit.
+__device__ inline double spheroid_distance_normal(double a, double b, const double *y, double *g) {
+  const double y0 = fabs(y[0]), r = sqrt(y[1] * y[1] + y[2] * y[2]);
+  double x0, x1;
+  if (a >= b) ellipse_nearest(a, b, y0, r, x0, x1);
+  else ellipse_nearest(b, a, r, y0, x1, x0);
+  const double d = a >= b ? sqrt((x0 - y0) * (x0 - y0) + (x1 - r) * (x1 - r))
+                          : sqrt((x1 - r) * (x1 - r) + (x0 - y0) * (x0 - y0));
+  const double n0 = x0 / (a * a), n1 = x1 / (b * b);
+  const double nn = 1.0 / sqrt(n0 * n0 + n1 * n1);
+  g[0] = copysign(n0 * nn, y[0]);
+  if (r > 0.0) {
+    g[1] = n1 * nn * y[1] / r;
+    g[2] = n1 * nn * y[2] / r;
+  } else {  // on the axis: the nearest points form a ring; one of them
+    g[1] = n1 * nn;
+    g[2] = 0.0;
+  }
+  const double k = (y[0] * y[0]) / (a * a) + (y[1] * y[1] + y[2] * y[2]) / (b * b);
+  return k <= 1.0 ? -d : d;
 }
 
 // Unit gradient of the body-frame signed distance at y: the outward normal
@@ -924,22 +950,7 @@ __device__ inline void body_sdf_normal(const Lattice &L, const DevParticle &P, c
     return;
   }
   if (P.shape == 2) {
-    // symmetry axis body x (semi-axis a), radial semi-axis b
-    const double a = P.prm[0], b = P.prm[1];
-    const double y0 = fabs(y[0]), r = sqrt(y[1] * y[1] + y[2] * y[2]);
-    double x0, x1;
-    if (a >= b) ellipse_nearest(a, b, y0, r, x0, x1);
-    else ellipse_nearest(b, a, r, y0, x1, x0);
-    const double n0 = x0 / (a * a), n1 = x1 / (b * b);
-    const double nn = 1.0 / sqrt(n0 * n0 + n1 * n1);
-    g[0] = copysign(n0 * nn, y[0]);
-    if (r > 0.0) {
-      g[1] = n1 * nn * y[1] / r;
-      g[2] = n1 * nn * y[2] / r;
-    } else {  // on the axis: the nearest points form a ring; one of them
-      g[1] = n1 * nn;
-      g[2] = 0.0;
-    }
+    spheroid_distance_normal(P.prm[0], P.prm[1], y, g);
     return;
   }
   const double h = 1e-5;
@@ -1115,10 +1126,14 @@ __device__ inline void pair_side(const Lattice &L, const DevParticle &A, const D
         const double kk = yb[0] * yb[0] / (B.prm[0] * B.prm[0]) + (yb[1] * yb[1] + yb[2] * yb[2]) / (B.prm[1] * B.prm[1]);
         far = (sqrt(kk) - 1.0) * fmin(B.prm[0], B.prm[1]) >= zeta;
       }
-      const double d = far ? zeta : body_sdf<MESH>(L, B, yb);
+      // a spheroid's distance and gradient come from one nearest-point iteration
+      double gb[3];
+      const double d = far ? zeta
+                           : (B.shape == 2 ? spheroid_distance_normal(B.prm[0], B.prm[1], yb, gb)
+                                           : body_sdf<MESH>(L, B, yb));
       if (d < zeta) {
-        double gb[3], g[3];
-        body_sdf_normal<MESH>(L, B, yb, gb);
+        double g[3];
+        if (B.shape != 2) body_sdf_normal<MESH>(L, B, yb, gb);
         rot(B.R, gb, g);
         const double w = 0.5 * K * a * (zeta - d);
         const double f[3] = {w * g[0], w * g[1], w * g[2]};
