@@ -171,7 +171,9 @@ int hlbm_set_fields(hlbm_ctx *ctx, const double *rho, const double *u);
  * Newton-Euler update in FP64 -> particle-to-lattice coupling with the
  * updated particles -> fused collide and stream with the exact-difference
  * source.  Asynchronous: errors raised inside kernels are reported by the
- * next hlbm_get_* call. */
+ * next hlbm_get_* call.  Runs are bitwise reproducible on a given GPU: every
+ * sum runs in a fixed order (lists filled by atomic appends are ranked by
+ * particle index before they are summed; no floating-point atomics). */
 int hlbm_step(hlbm_ctx *ctx, int32_t nsteps);
 
 /* Set the closed triangle mesh of HLBM_MESH particles: vertices[nv][3] in
