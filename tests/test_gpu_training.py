@@ -2,6 +2,7 @@
 C ABI: the Adam update of the FP32 master parameters (two consecutive steps,
 fed the GPU's own gradients) against the FP64 Adam of oracle/mlp_oracle.py,
 the packed operands the step updates in place against a full repack,
+the bitwise reproducibility of a training,
 and the exact-distance training samples the GPU generator draws against the
 oracle's signed distance at the returned points.
 
@@ -113,3 +114,24 @@ def test_samples_match_oracle_sdf(H, shape):
     assert inband >= share - 0.02
     # the counter-based generator gives every sample its own draw
     assert len(np.unique(s[:, 0])) > 0.99 * n
+
+
+def test_training_is_bitwise_reproducible(H):
+    """The training path has no floating-point atomics (fixed-order partial
+    sums, one workgroup per 64 parameters for the Adam step), so two
+    trainings from the same parameters and seed end at the same network bit
+    for bit, in two separate contexts."""
+    _log("gpu: training reproducibility, 2 x 300 Adam steps")
+    prm = W.equal_volume_params(W.SPHEROID, 6.0)
+    res = []
+    for _ in range(2):
+        sim = _sim(H)
+        sim.mlp_set_params(W.SPHEROID, W.mlp_init_params(5))
+        rep = sim.train_indicator(W.SPHEROID, prm[:2], samples=100_000, holdout=10_000, iterations=300,
+                                  batch=8192, gate_rms=1.0, gate_max=10.0)
+        res.append((sim.mlp_get_params(W.SPHEROID), rep))
+        sim.close()
+    (t0, r0), (t1, r1) = res
+    assert r0["loss_last"] < r0["loss_first"]
+    np.testing.assert_array_equal(t0, t1)
+    assert r0["loss_last"] == r1["loss_last"] and r0["rms_err"] == r1["rms_err"]
